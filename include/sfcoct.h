@@ -1,0 +1,183 @@
+/*
+ * sfcoct.h -- C ABI of the MI355X (gfx950) library for space-filling-curve
+ * reordering, linear octrees and neighbourhood search in 3D point clouds,
+ * after arXiv 2603.06771 ("Efficient Neighbourhood Search in 3D Point Clouds
+ * Through Space-Filling Curves and Linear Octrees").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers into caller-owned memory unless
+ *   stated otherwise.  The library never allocates or frees device memory.
+ * - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *   NULL is the default stream) and performs no host synchronisation.
+ * - Workspace protocol: a call that takes (ws, ws_bytes) with ws == NULL only
+ *   stores the workspace size it needs in *ws_bytes (a host pointer) and runs
+ *   nothing.  A call with ws != NULL and *ws_bytes below that size returns
+ *   SFC_EWORKSPACE and runs nothing.  Workspace must be 256-byte aligned.
+ *   Its contents are scratch and need no initialisation.
+ * - Return codes are sfc_status values.  SFC_EINVAL and SFC_EWORKSPACE are
+ *   returned before anything is enqueued, so no output is touched.
+ *   SFC_EHIP reports a failed launch; sfc_last_error() gives the message.
+ * - Coordinates are IEEE binary32 and must be finite.  Indices are uint32,
+ *   so a cloud holds at most 2^32 - 1 points.
+ * - Arithmetic contract: every fp32 expression is evaluated as written, with
+ *   round-to-nearest-even, no fused multiply-add and denormals kept, so the
+ *   results are bit-for-bit those of the definitions below.
+ * - Calls on one stream are ordered; calls that share output buffers on
+ *   different streams race and are the caller's responsibility.
+ */
+#ifndef SFCOCT_H
+#define SFCOCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFC_OK = 0,
+    SFC_EINVAL = -1,      /* bad argument (null pointer, size, enum) */
+    SFC_EWORKSPACE = -2,  /* workspace too small or misaligned */
+    SFC_ECAPACITY = -3,   /* reserved: output capacity checks are device-side */
+    SFC_EHIP = -4,        /* a HIP runtime call or kernel launch failed */
+    SFC_ENOTSUP = -5      /* valid but unsupported request (e.g. k > 32) */
+} sfc_status;
+
+/* Space-filling curves of Section 4 (4.1 Morton, 4.2 Hilbert). */
+typedef enum { SFC_MORTON = 0, SFC_HILBERT = 1 } sfc_curve;
+
+/* Search kernels of Section 3.2 (Definition of a search kernel). */
+typedef enum { SFC_SPHERE = 0, SFC_CIRCLE = 1, SFC_CUBE = 2, SFC_SQUARE = 3 } sfc_kernel;
+
+/* Discretisation frame of Section 4, steps 1-2: cell_a = floor((x_a - lo_a) *
+ * scale), clamped to [0, 2^bits - 1]; scale = 2^bits / E with E the largest
+ * side of the cloud's bounding box (E = 1 for a degenerate or empty cloud). */
+typedef struct sfc_frame {
+    float lo[3];
+    float scale;
+    int32_t bits;   /* L, levels per axis, 1..21 */
+    int32_t curve;  /* sfc_curve */
+} sfc_frame;
+
+/* Octree node record: the node's point range [begin, end) in sorted order
+ * (the paper's internalRanges, Section 5.1) and the tight bounding box of its
+ * points (lo = +inf, hi = -inf when the node is empty). 32 bytes. */
+typedef struct sfc_node {
+    float lo[3];
+    uint32_t begin;
+    float hi[3];
+    uint32_t end;
+} sfc_node;
+
+/* Device-resident counts written by build_linear_octree. */
+typedef struct sfc_tree_info {
+    int64_t n_points;
+    int64_t n_internal;
+    int64_t n_leaves;   /* = 7 * n_internal + 1 (complete octree) */
+    int64_t n_nodes;    /* = n_internal + n_leaves */
+    int32_t depth;      /* deepest level holding a node */
+    int32_t status;     /* 0 = ok */
+    int64_t level_nodes_off[23]; /* first node index of each level (BFS order) */
+} sfc_tree_info;
+
+/* Non-owning view of a built octree; every pointer is a device address inside
+ * the caller's tree memory.  Filled in by build_linear_octree (host struct).
+ * Nodes are stored level by level (breadth first), ordered by code inside a
+ * level; the 8 children of an internal node are consecutive. */
+typedef struct sfc_octree {
+    int64_t n;            /* points */
+    int64_t max_nodes;    /* capacity of the node arrays */
+    int64_t max_leaves;   /* capacity of leaves / counts */
+    int32_t bits;
+    int32_t curve;
+    uint32_t leaf_size;   /* N_max of Section 5.1 */
+    uint32_t reserved;
+    sfc_frame *frame;     /* [1] frame used for the codes */
+    float *points;        /* [4n] sorted cloud {x, y, z, bits(original index)} */
+    uint64_t *keys;       /* [n] sorted codes */
+    uint32_t *perm;       /* [n] original index of the i-th sorted point */
+    uint64_t *leaves;     /* [n_leaves + 1] the paper's leaves array (codes) */
+    uint32_t *counts;     /* [n_leaves] points per leaf */
+    sfc_node *nodes;      /* [n_nodes] ranges and boxes, breadth-first */
+    int32_t *child;       /* [n_nodes] index of the first child, -1 for a leaf */
+    uint64_t *node_key;   /* [n_nodes] first code of the node */
+    uint8_t *node_level;  /* [n_nodes] level (0 = root) */
+    sfc_tree_info *info;  /* [1] actual counts */
+} sfc_octree;
+
+/* Section 4 (steps 1-2, 4.1, 4.2), reorder step 1: codes of every point.
+ *   xyz    [3n] fp32, x y z interleaved, original order (device)
+ *   curve  sfc_curve; bits = L in 1..21 (the paper uses 21, a 63-bit code)
+ *   frame  [1] device output: the frame of the cloud
+ *   keys   [n] device output: key[i] = C(cell(xyz[i])) < 8^bits
+ * n == 0 is valid (frame lo = 0, scale = 2^bits). */
+int encode_sfc(const float *xyz, int64_t n, int curve, int bits, sfc_frame *frame, uint64_t *keys,
+               void *ws, size_t *ws_bytes, void *stream);
+
+/* Bytes of tree memory build_linear_octree needs for n points and the given
+ * leaf threshold (an upper bound on every array; host output). */
+int octree_bytes(int64_t n, uint32_t leaf_size, int bits, size_t *bytes);
+
+/* Sections 4 and 5.1: encode, sort ascending by code (ties by original
+ * index), gather the sorted cloud, and build the complete linear octree in
+ * which a node is split into its 8 octants iff it holds more than leaf_size
+ * points and its level is below bits.  Computes leaves, counts, every node's
+ * point range (internalRanges) and tight bounding box, and the child links.
+ *   xyz        [3n] fp32 original cloud (device, read only)
+ *   tree_mem   device memory of at least octree_bytes(n, leaf_size, bits)
+ *   tree_out   host output: the view of the tree inside tree_mem
+ * leaf_size >= 1.  Node counts are written to tree_out->info on the device. */
+int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32_t leaf_size,
+                        void *tree_mem, size_t tree_bytes, sfc_octree *tree_out, void *ws,
+                        size_t *ws_bytes, void *stream);
+
+/* Section 3.2 with the pruning of Section 5.1 (neighboursPrune): for every
+ * query c and the chosen kernel, the set {j : pred(p_j, c, r)} of ORIGINAL
+ * point indices, as CSR.  Predicates, with dx = p - c per axis in fp32:
+ *   SPHERE (dx*dx + dy*dy) + dz*dz < r*r     CIRCLE dx*dx + dy*dy < r*r
+ *   CUBE   |dx| < r, |dy| < r, |dz| < r      SQUARE |dx| < r, |dy| < r
+ * r <= 0 gives empty rows; r must not be NaN or infinite.
+ *   tree      built octree (host struct, device pointers)
+ *   queries   [3nq] fp32 centres (device), or NULL: every cloud point is a
+ *             query and row i is the point at sorted position i (nq == n)
+ *   counts    [nq] output neighbour counts
+ *   offsets   [nq+1] output exclusive prefix sums of counts (row starts)
+ *   indices   [capacity] output neighbour lists, or NULL for counts only.
+ *             Written only if offsets[nq] <= capacity (checked on the device);
+ *             otherwise nothing is written and the caller retries with
+ *             capacity >= offsets[nq].  Order inside a row is unspecified but
+ *             deterministic.
+ *   flags     bit 0 (SFC_REUSE_COUNTS): counts/offsets already hold the
+ *             result of a count call with identical arguments; skip it.
+ *             bit 1 (SFC_NO_PRUNE): no containment shortcut (neighboursLin).
+ */
+#define SFC_REUSE_COUNTS 1u
+#define SFC_NO_PRUNE 2u
+int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
+                  uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
+                  uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
+
+/* Section 3.3: the k nearest cloud points of every query, as the k smallest
+ * pairs (d2, original index) in lexicographic order, ascending, where d2 is
+ * the SPHERE expression above.  Ties in d2 are broken by the smaller index; a
+ * query that is a cloud point finds itself at d2 = 0.  When k > n the missing
+ * entries are (0xFFFFFFFF, +inf).
+ *   queries  [3nq] fp32 (device) or NULL (every point, rows in sorted order)
+ *   idx      [nq*k] output indices;  d2 [nq*k] output squared distances
+ * 1 <= k <= 32 (SFC_ENOTSUP above). */
+int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx,
+               float *d2, void *ws, size_t *ws_bytes, void *stream);
+
+/* Message of the last SFC_EINVAL / SFC_EHIP on the calling thread. */
+const char *sfc_last_error(void);
+
+/* Library version string. */
+const char *sfc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFCOCT_H */

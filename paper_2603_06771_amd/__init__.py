@@ -1,0 +1,201 @@
+"""MI355X (gfx950) space-filling-curve reordering, linear octrees and
+neighbourhood search for 3D point clouds (arXiv 2603.06771).
+
+Thin PyTorch-facing wrappers over the C ABI of libsfcoct.so (include/sfcoct.h):
+tensors provide device memory, torch's current stream provides ordering.  All
+computation runs in the library's HIP kernels; nothing here falls back to the
+CPU.  Importing the package does not load the library; the first call does.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _binding as B
+
+__all__ = ["encode_sfc", "build_linear_octree", "radius_search", "knn_search", "Octree",
+           "CURVES", "KERNELS", "library_path"]
+
+CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
+KERNELS = {"sphere": B.SPHERE, "circle": B.CIRCLE, "cube": B.CUBE, "square": B.SQUARE}
+library_path = B.LIB_PATH
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise B.SfcError("no GPU visible: the sfcoct library runs on MI355X only")
+    return torch
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _xyz(torch, xyz):
+    if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
+        raise ValueError("expected a CUDA float32 tensor of shape (n, 3)")
+    return xyz.contiguous()
+
+
+def _ws(torch, nbytes: int):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def _code(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def encode_sfc(xyz, curve="morton", bits: int = 21):
+    """Section 4: frame and codes of every point.  Returns (keys int64 tensor
+    holding the uint64 codes, frame as a host SfcFrame)."""
+    torch = _torch()
+    L = B.load()
+    xyz = _xyz(torch, xyz)
+    n = xyz.shape[0]
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    frame = torch.empty(ctypes.sizeof(B.SfcFrame), dtype=torch.uint8, device="cuda")
+    need = ctypes.c_size_t(0)
+    B.check(L.encode_sfc(_ptr(xyz), n, _code(CURVES, curve), bits, _ptr(frame), _ptr(keys), None,
+                         ctypes.byref(need), None), "encode_sfc(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.encode_sfc(_ptr(xyz), n, _code(CURVES, curve), bits, _ptr(frame), _ptr(keys), _ptr(ws),
+                         ctypes.byref(need), _stream(torch)), "encode_sfc")
+    return keys, frame
+
+
+@dataclass
+class Octree:
+    """A built linear octree: `mem` owns the device memory, `view` is the C
+    struct of device pointers into it."""
+    mem: object
+    view: B.SfcOctree
+    curve: int
+    bits: int
+    leaf_size: int
+    n: int
+
+    def _slice(self, ptr, count, dtype, elem):
+        off = ptr - self.mem.data_ptr()
+        return self.mem[off:off + count * elem].view(dtype)
+
+    def info(self) -> dict:
+        torch = _torch()
+        raw = self._slice(self.view.info, ctypes.sizeof(B.SfcTreeInfo), torch.uint8, 1).cpu().numpy()
+        st = B.SfcTreeInfo.from_buffer_copy(raw.tobytes())
+        return {"n_points": st.n_points, "n_internal": st.n_internal, "n_leaves": st.n_leaves,
+                "n_nodes": st.n_nodes, "depth": st.depth, "status": st.status,
+                "level_nodes_off": list(st.level_nodes_off)}
+
+    def frame(self) -> B.SfcFrame:
+        torch = _torch()
+        raw = self._slice(self.view.frame, ctypes.sizeof(B.SfcFrame), torch.uint8, 1).cpu().numpy()
+        return B.SfcFrame.from_buffer_copy(raw.tobytes())
+
+    # views (tensors sharing the tree memory); counts from info()
+    def points(self):
+        torch = _torch()
+        return self._slice(self.view.points, 4 * self.n, torch.float32, 4).view(self.n, 4)
+
+    def keys(self):
+        torch = _torch()
+        return self._slice(self.view.keys, self.n, torch.int64, 8)
+
+    def perm(self):
+        torch = _torch()
+        return self._slice(self.view.perm, self.n, torch.int32, 4)
+
+    def arrays(self, info: dict | None = None) -> dict:
+        """leaves / counts / nodes / child / node_key / node_level sized by info()."""
+        torch = _torch()
+        info = info or self.info()
+        nl, nn = info["n_leaves"], info["n_nodes"]
+        v = self.view
+        return {
+            "leaves": self._slice(v.leaves, nl + 1, torch.int64, 8),
+            "counts": self._slice(v.counts, nl, torch.int32, 4),
+            "nodes": self._slice(v.nodes, 8 * nn, torch.float32, 4).view(nn, 8),
+            "child": self._slice(v.child, nn, torch.int32, 4),
+            "node_key": self._slice(v.node_key, nn, torch.int64, 8),
+            "node_level": self._slice(v.node_level, nn, torch.uint8, 1),
+        }
+
+
+def build_linear_octree(xyz, curve="morton", bits: int = 21, leaf_size: int = 32) -> Octree:
+    """Sections 4 and 5.1: encode, sort, reorder and build the complete linear
+    octree (split while a node holds more than leaf_size points)."""
+    torch = _torch()
+    L = B.load()
+    xyz = _xyz(torch, xyz)
+    n = xyz.shape[0]
+    c = _code(CURVES, curve)
+    tb = ctypes.c_size_t(0)
+    B.check(L.octree_bytes(n, leaf_size, bits, ctypes.byref(tb)), "octree_bytes")
+    mem = torch.empty(tb.value, dtype=torch.uint8, device="cuda")
+    need = ctypes.c_size_t(0)
+    view = B.SfcOctree()
+    B.check(L.build_linear_octree(_ptr(xyz), n, c, bits, leaf_size, _ptr(mem), tb.value, ctypes.byref(view),
+                                  None, ctypes.byref(need), None), "build_linear_octree(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.build_linear_octree(_ptr(xyz), n, c, bits, leaf_size, _ptr(mem), tb.value, ctypes.byref(view),
+                                  _ptr(ws), ctypes.byref(need), _stream(torch)), "build_linear_octree")
+    return Octree(mem=mem, view=view, curve=c, bits=bits, leaf_size=leaf_size, n=n)
+
+
+def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, capacity: int | None = None,
+                  prune: bool = True):
+    """Section 3.2 / 5.1: CSR (counts int32, offsets int64 [nq+1], indices
+    int32 original point indices).  queries=None searches around every cloud
+    point, rows in sorted (curve) order.  Without a capacity the count pass
+    runs first and the host reads the total before the fill pass."""
+    torch = _torch()
+    L = B.load()
+    if queries is not None:
+        queries = _xyz(torch, queries)
+        nq = queries.shape[0]
+    else:
+        nq = tree.n
+    k = _code(KERNELS, kernel)
+    flags = 0 if prune else B.NO_PRUNE
+    counts = torch.empty(nq, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    need = ctypes.c_size_t(0)
+    args = (ctypes.byref(tree.view), _ptr(queries), nq, k, float(r), _ptr(counts), _ptr(offsets))
+    B.check(L.radius_search(*args, None, 0, flags, None, ctypes.byref(need), None), "radius_search(size)")
+    ws = _ws(torch, need.value)
+    stream = _stream(torch)
+    if capacity is None:
+        B.check(L.radius_search(*args, None, 0, flags, _ptr(ws), ctypes.byref(need), stream), "radius_search(count)")
+        total = int(offsets[nq].item())
+        indices = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        B.check(L.radius_search(*args, _ptr(indices), total, flags | B.REUSE_COUNTS, _ptr(ws), ctypes.byref(need),
+                                stream), "radius_search(fill)")
+        return counts, offsets, indices[:total]
+    indices = torch.empty(max(int(capacity), 1), dtype=torch.int32, device="cuda")
+    B.check(L.radius_search(*args, _ptr(indices), int(capacity), flags, _ptr(ws), ctypes.byref(need), stream),
+            "radius_search")
+    return counts, offsets, indices
+
+
+def knn_search(tree: Octree, queries=None, k: int = 8):
+    """Section 3.3: (idx int32 [nq, k], d2 float32 [nq, k]), each row ascending
+    by (d2, index); queries=None uses every cloud point in sorted order."""
+    torch = _torch()
+    L = B.load()
+    if queries is not None:
+        queries = _xyz(torch, queries)
+        nq = queries.shape[0]
+    else:
+        nq = tree.n
+    idx = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    d2 = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    need = ctypes.c_size_t(0)
+    args = (ctypes.byref(tree.view), _ptr(queries), nq, int(k), _ptr(idx), _ptr(d2))
+    B.check(L.knn_search(*args, None, ctypes.byref(need), None), "knn_search(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.knn_search(*args, _ptr(ws), ctypes.byref(need), _stream(torch)), "knn_search")
+    return idx, d2

@@ -1,0 +1,85 @@
+"""ctypes binding of libsfcoct.so (the C ABI declared in include/sfcoct.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and the stream
+(torch.cuda.current_stream()).  There is no CPU fallback: if the library is
+missing or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfcoct.so")
+
+SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_ECAPACITY, SFC_EHIP, SFC_ENOTSUP = 0, -1, -2, -3, -4, -5
+MORTON, HILBERT = 0, 1
+SPHERE, CIRCLE, CUBE, SQUARE = 0, 1, 2, 3
+REUSE_COUNTS, NO_PRUNE = 1, 2
+
+# every exported symbol of include/sfcoct.h
+EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
+           "sfc_last_error", "sfc_version")
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+U32 = ctypes.c_uint32
+U64 = ctypes.c_uint64
+SZ = ctypes.c_size_t
+F32 = ctypes.c_float
+
+
+class SfcFrame(ctypes.Structure):
+    _fields_ = [("lo", F32 * 3), ("scale", F32), ("bits", I32), ("curve", I32)]
+
+
+class SfcTreeInfo(ctypes.Structure):
+    _fields_ = [("n_points", I64), ("n_internal", I64), ("n_leaves", I64), ("n_nodes", I64),
+                ("depth", I32), ("status", I32), ("level_nodes_off", I64 * 23)]
+
+
+class SfcOctree(ctypes.Structure):
+    _fields_ = [
+        ("n", I64), ("max_nodes", I64), ("max_leaves", I64),
+        ("bits", I32), ("curve", I32), ("leaf_size", U32), ("reserved", U32),
+        ("frame", P), ("points", P), ("keys", P), ("perm", P), ("leaves", P), ("counts", P),
+        ("nodes", P), ("child", P), ("node_key", P), ("node_level", P), ("info", P),
+    ]
+
+
+class SfcError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise SfcError(f"{path} not found: build it with `python -m paper_2603_06771_amd.build`")
+    L = ctypes.CDLL(path)
+    L.encode_sfc.argtypes = [P, I64, I32, I32, P, P, P, ctypes.POINTER(SZ), P]
+    L.octree_bytes.argtypes = [I64, U32, I32, ctypes.POINTER(SZ)]
+    L.build_linear_octree.argtypes = [P, I64, I32, I32, U32, P, SZ, ctypes.POINTER(SfcOctree), P,
+                                      ctypes.POINTER(SZ), P]
+    L.radius_search.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, F32, P, P, P, U64, U32, P,
+                                ctypes.POINTER(SZ), P]
+    L.knn_search.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, P, P, P, ctypes.POINTER(SZ), P]
+    L.sfc_last_error.restype = ctypes.c_char_p
+    L.sfc_version.restype = ctypes.c_char_p
+    for name in ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search"):
+        getattr(L, name).restype = I32
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> None:
+    if rc != SFC_OK:
+        msg = load().sfc_last_error().decode(errors="replace")
+        raise SfcError(f"{what} failed with status {rc}: {msg}")

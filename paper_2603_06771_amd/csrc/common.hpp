@@ -1,0 +1,110 @@
+// Shared device/host helpers of the gfx950 library (wave64 primitives, fp32
+// operations with explicit rounding, launch checks).  Device code is built
+// with -ffp-contract=off and the *_rn intrinsics below, so every fp32
+// expression is evaluated exactly as written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sfcoct.h"
+
+namespace sfc {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- host side
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+#define SFC_LAUNCH_CHECK(what)                                       \
+    do {                                                             \
+        hipError_t _e = hipGetLastError();                           \
+        if (_e != hipSuccess) return ::sfc::hip_fail(_e, what);      \
+    } while (0)
+
+#define SFC_HIP_TRY(call)                                            \
+    do {                                                             \
+        hipError_t _e = (call);                                      \
+        if (_e != hipSuccess) return ::sfc::hip_fail(_e, #call);     \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Sequential carving of one caller buffer into aligned sub-arrays.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return align_up(off, 256); }
+};
+
+inline int grid_for(int64_t n, int block, int cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+// -------------------------------------------------------------- device side
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const int l = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(v, o);
+        if (l >= o) v += y;
+    }
+    return v;
+}
+
+// fp32 operations with round-to-nearest-even and no contraction
+__device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b); }
+__device__ __forceinline__ float fadd(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ float fmul(float a, float b) { return __fmul_rn(a, b); }
+
+// order-preserving int image of a float, for integer atomics on floats
+__device__ __forceinline__ int ordered_int(float f) {
+    int i = __float_as_int(f);
+    return i >= 0 ? i : (i ^ 0x7FFFFFFF);
+}
+__device__ __forceinline__ float ordered_float(int i) {
+    return __int_as_float(i >= 0 ? i : (i ^ 0x7FFFFFFF));
+}
+
+// 8 XCDs take workgroups round robin; give each XCD a contiguous range of
+// work items so that neighbouring items share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t block, int64_t grid) {
+    const int64_t per = (grid + 7) / 8;
+    return (block & 7) * per + (block >> 3);
+}
+inline int64_t xcd_grid(int64_t items) { return ((items + 7) / 8) * 8; }
+
+}  // namespace sfc

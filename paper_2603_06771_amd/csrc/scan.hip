@@ -1,0 +1,110 @@
+// Device-wide exclusive prefix sum of uint32 counts (reduce-then-scan):
+//   k_scan_tiles : each block scans a tile of 2048 counts locally and records
+//                  the tile total
+//   k_scan_sums  : one block scans the tile totals
+//   k_scan_add   : tiles add their offset; the grand total goes to out[n]
+// Used for CSR row offsets, radix-sort digit offsets and node emission.
+#include "internal.hpp"
+
+namespace sfc {
+
+namespace {
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+template <typename T>
+__device__ T block_exclusive_sum(T v, T *s_wave, T *total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const T incl = wave_inclusive_sum(v);
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    T wave_off = 0, all = 0;
+    for (int w = 0; w < kScanBlock / kWave; ++w) {
+        const T t = s_wave[w];
+        if (w < wave) wave_off += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return wave_off + incl - v;
+}
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const uint32_t *__restrict__ in, int64_t n,
+                                                           T *__restrict__ out, T *__restrict__ sums) {
+    __shared__ T s_wave[kScanBlock / kWave];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
+    T v[kScanItems];
+    T thread_sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? static_cast<T>(in[base + i]) : T(0);
+        thread_sum += v[i];
+    }
+    T total;
+    T run = block_exclusive_sum<T>(thread_sum, s_wave, &total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(T *sums, int64_t nb) {
+    __shared__ T s_wave[kScanBlock / kWave];
+    T carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanBlock) {
+        const int64_t i = base + threadIdx.x;
+        const T v = i < nb ? sums[i] : T(0);
+        T total;
+        const T ex = block_exclusive_sum<T>(v, s_wave, &total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(T *__restrict__ out, int64_t n, const T *__restrict__ sums,
+                                                         int64_t nb, int write_total) {
+    const T off = sums[blockIdx.x];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    for (int i = threadIdx.x; i < kScanTile; i += kScanBlock) {
+        const int64_t j = base + i;
+        if (j < n) out[j] += off;
+    }
+    if (write_total && blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+size_t scan_ws_bytes(int64_t n) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile + 1;
+    return align_up(static_cast<size_t>(nb + 1) * sizeof(uint64_t), 256);
+}
+
+template <typename T>
+static int scan_impl(const uint32_t *in, int64_t n, T *out, bool write_total, void *ws, hipStream_t s) {
+    const int64_t nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 0;
+    T *sums = static_cast<T *>(ws);
+    if (nb > 0) {
+        k_scan_tiles<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, out, sums);
+        SFC_LAUNCH_CHECK("k_scan_tiles");
+    }
+    k_scan_sums<T><<<1, kScanBlock, 0, s>>>(sums, nb);
+    SFC_LAUNCH_CHECK("k_scan_sums");
+    k_scan_add<T><<<static_cast<unsigned>(nb > 0 ? nb : 1), kScanBlock, 0, s>>>(out, n, sums, nb, write_total ? 1 : 0);
+    SFC_LAUNCH_CHECK("k_scan_add");
+    return SFC_OK;
+}
+
+int scan_u32_to_u32(const uint32_t *in, int64_t n, uint32_t *out, bool write_total, void *ws, hipStream_t s) {
+    return scan_impl<uint32_t>(in, n, out, write_total, ws, s);
+}
+int scan_u32_to_u64(const uint32_t *in, int64_t n, uint64_t *out, bool write_total, void *ws, hipStream_t s) {
+    return scan_impl<uint64_t>(in, n, out, write_total, ws, s);
+}
+
+}  // namespace sfc

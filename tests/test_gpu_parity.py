@@ -1,0 +1,248 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle on the same
+seeded inputs.  Bit-exact throughout: codes, permutation, octree arrays,
+neighbour sets and k-NN lists (integer results and fp32 values computed by the
+same fixed expressions on both sides)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_06771_amd import datagen
+from tests._parity import announce, assert_csr_equal
+
+pytestmark = pytest.mark.gpu
+
+CURVES = ["morton", "hilbert"]
+KERNELS = ["sphere", "circle", "cube", "square"]
+
+
+@pytest.fixture(scope="module")
+def sfc():
+    import torch  # noqa: F401
+    import paper_2603_06771_amd as sfc
+    return sfc
+
+
+def _cloud(kind, n, seed=3):
+    if kind == "uniform":
+        return datagen.uniform(n, seed=seed)
+    if kind == "lidar":
+        return datagen.lidar_tile(n, seed=seed)
+    base = datagen.uniform(n - n // 8, seed=seed)
+    return datagen.with_duplicates(base, n // 8, seed=seed)
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("curve", CURVES)
+@pytest.mark.parametrize("kind,n", [("uniform", 1), ("uniform", 4097), ("lidar", 100003), ("dup", 30011)])
+@pytest.mark.parametrize("bits", [21, 7])
+def test_encode(sfc, curve, kind, n, bits):
+    announce(f"encode {curve} {kind} n={n} bits={bits}")
+    pts = _cloud(kind, n)
+    keys, frame = sfc.encode_sfc(_dev(pts), curve, bits)
+    import torch
+    torch.cuda.synchronize()
+    rk, lo, s = oracle.encode(pts, curve, bits)
+    assert np.array_equal(_u64(keys), rk)
+    f = np.frombuffer(frame.cpu().numpy().tobytes(), dtype=np.float32, count=4)
+    assert np.array_equal(f[:3], lo) and f[3] == s
+
+
+def test_encode_empty(sfc):
+    import torch
+    keys, frame = sfc.encode_sfc(torch.zeros((0, 3), dtype=torch.float32, device="cuda"), "hilbert", 21)
+    torch.cuda.synchronize()
+    f = np.frombuffer(frame.cpu().numpy().tobytes(), dtype=np.float32, count=4)
+    assert keys.numel() == 0 and list(f) == [0, 0, 0, 2.0 ** 21]
+
+
+def _check_tree(sfc, pts, curve, bits, leaf):
+    import torch
+    t = sfc.build_linear_octree(_dev(pts), curve, bits, leaf)
+    torch.cuda.synchronize()
+    info = t.info()
+    rk, lo, s = oracle.encode(pts, curve, bits)
+    ks, perm = oracle.sort(rk)
+    ref = oracle.build_tree(pts, ks, perm, bits, leaf)
+    assert info["status"] == 0
+    assert np.array_equal(_u64(t.keys()), ks)
+    assert np.array_equal(t.perm().cpu().numpy().view(np.uint32), perm)
+    p = t.points().cpu().numpy()
+    assert np.array_equal(p[:, :3], pts[perm])
+    assert np.array_equal(p[:, 3].view(np.uint32), perm)
+    assert info["n_internal"] == ref["n_internal"] and info["n_leaves"] == ref["n_leaves"]
+    assert info["n_nodes"] == ref["n_nodes"]
+    arr = t.arrays(info)
+    assert np.array_equal(_u64(arr["leaves"]), ref["leaves"])
+    assert np.array_equal(arr["counts"].cpu().numpy().view(np.uint32), ref["counts"])
+    assert np.array_equal(arr["node_level"].cpu().numpy().astype(np.int32), ref["node_level"])
+    assert np.array_equal(_u64(arr["node_key"]), ref["node_start"])
+    nodes = arr["nodes"].cpu().numpy()
+    assert np.array_equal(nodes[:, 3].view(np.uint32).astype(np.int64), ref["node_begin"])
+    assert np.array_equal(nodes[:, 7].view(np.uint32).astype(np.int64), ref["node_end"])
+    assert np.array_equal(arr["child"].cpu().numpy().astype(np.int64), ref["node_child"])
+    box = np.concatenate([nodes[:, 0:3], nodes[:, 4:7]], axis=1)
+    assert np.array_equal(box, ref["node_box"])
+    return t
+
+
+@pytest.mark.parametrize("curve", CURVES)
+@pytest.mark.parametrize("kind,n,leaf", [("uniform", 100003, 32), ("lidar", 65537, 16), ("dup", 20000, 8),
+                                         ("lidar", 9000, 128), ("uniform", 5, 8), ("uniform", 0, 8)])
+def test_build(sfc, curve, kind, n, leaf):
+    announce(f"build {curve} {kind} n={n} leaf={leaf}")
+    pts = _cloud(kind, n) if n else np.zeros((0, 3), np.float32)
+    _check_tree(sfc, pts, curve, 21, leaf)
+
+
+def test_build_coarse_levels(sfc):
+    # few levels: many level-L leaves above the threshold (duplicate cells)
+    announce("build coarse bits=3")
+    pts = _cloud("dup", 5000)
+    _check_tree(sfc, pts, "hilbert", 3, 4)
+    _check_tree(sfc, pts, "morton", 2, 16)
+
+
+def _radius_case(sfc, pts, curve, leaf, kernel, r, queries=None, prune=True):
+    import torch
+    t = sfc.build_linear_octree(_dev(pts), curve, 21, leaf)
+    q = None if queries is None else _dev(queries)
+    c, o, i = sfc.radius_search(t, q, kernel, r, prune=prune)
+    torch.cuda.synchronize()
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    qpts = pts[perm] if queries is None else queries
+    ref = oracle.radius_search(pts, qpts, kernel, r)
+    assert_csr_equal((c.cpu().numpy(), o.cpu().numpy(), i.cpu().numpy()), ref, f"{kernel} r={r}")
+    return c, o, i
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("curve", CURVES)
+def test_radius_lidar(sfc, kernel, curve):
+    pts = _cloud("lidar", 60001, seed=11)
+    for r in (0.5, 1.0, 3.0):
+        announce(f"radius lidar {kernel} {curve} r={r}")
+        _radius_case(sfc, pts, curve, 32, kernel, r)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_radius_uniform_small_config(sfc, kernel):
+    # the 100k uniform configuration: Morton, leaf 32, r = 0.01 (and a larger r)
+    pts = _cloud("uniform", 100000, seed=datagen.SEED_UNIFORM)
+    for r in (0.01, 0.0212):
+        announce(f"radius uniform100k {kernel} r={r}")
+        _radius_case(sfc, pts, "morton", 32, kernel, r)
+
+
+@pytest.mark.parametrize("leaf", [1, 8, 64, 200])
+def test_radius_leaf_sizes_and_duplicates(sfc, leaf):
+    pts = _cloud("dup", 20000, seed=5)
+    for kernel in ("sphere", "square"):
+        announce(f"radius dup leaf={leaf} {kernel}")
+        _radius_case(sfc, pts, "hilbert", leaf, kernel, 0.03)
+
+
+def test_radius_nonpositive_and_tiny(sfc):
+    pts = _cloud("uniform", 3000, seed=2)
+    for r in (0.0, -1.0, 1e-30):
+        announce(f"radius r={r}")
+        c, o, i = _radius_case(sfc, pts, "morton", 8, "cube", r)
+        if r <= 0:
+            assert int(o[-1]) == 0
+
+
+def test_radius_external_queries(sfc):
+    rng = np.random.default_rng(4)
+    pts = _cloud("lidar", 40000, seed=8)
+    lo, hi = pts.min(0), pts.max(0)
+    q = (lo + (hi - lo) * rng.uniform(-0.1, 1.1, (7001, 3))).astype(np.float32)
+    for kernel in KERNELS:
+        announce(f"radius external {kernel}")
+        _radius_case(sfc, pts, "hilbert", 32, kernel, 2.0, queries=q)
+
+
+def test_radius_no_prune_flag(sfc):
+    pts = _cloud("lidar", 30000, seed=9)
+    announce("radius no-prune")
+    _radius_case(sfc, pts, "morton", 16, "sphere", 2.5, prune=False)
+
+
+def test_radius_capacity_protocol(sfc):
+    import torch
+    pts = _cloud("uniform", 20000, seed=6)
+    t = sfc.build_linear_octree(_dev(pts), "morton", 21, 32)
+    announce("radius capacity too small")
+    c, o, i = sfc.radius_search(t, None, "sphere", 0.05, capacity=10)
+    torch.cuda.synchronize()
+    total = int(o[-1])
+    assert total > 10
+    # nothing written: the buffer keeps whatever it held, the counts are valid
+    c2, o2, i2 = sfc.radius_search(t, None, "sphere", 0.05, capacity=total)
+    torch.cuda.synchronize()
+    assert torch.equal(c, c2) and torch.equal(o, o2)
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    ref = oracle.radius_search(pts, pts[perm], "sphere", 0.05)
+    assert_csr_equal((c2.cpu().numpy(), o2.cpu().numpy(), i2.cpu().numpy()), ref, "capacity")
+
+
+def test_radius_deterministic(sfc):
+    import torch
+    pts = _cloud("lidar", 50000, seed=10)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
+    announce("radius determinism")
+    a = sfc.radius_search(t, None, "sphere", 1.5)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = sfc.radius_search(t, None, "sphere", 1.5)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def _knn_case(sfc, pts, curve, leaf, k, queries=None):
+    import torch
+    t = sfc.build_linear_octree(_dev(pts), curve, 21, leaf)
+    q = None if queries is None else _dev(queries)
+    idx, d2 = sfc.knn_search(t, q, k)
+    torch.cuda.synchronize()
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    qpts = pts[perm] if queries is None else queries
+    ridx, rd2 = oracle.knn(pts, qpts, k)
+    gi = idx.cpu().numpy().view(np.uint32)
+    gd = d2.cpu().numpy()
+    bad = np.nonzero(np.any(gi != ridx, axis=1) | np.any(gd.view(np.uint32) != rd2.view(np.uint32), axis=1))[0]
+    assert bad.size == 0, f"k={k}: {bad.size} rows differ, first {bad[0]}: gpu {gi[bad[0]]} {gd[bad[0]]} " \
+                          f"oracle {ridx[bad[0]]} {rd2[bad[0]]}"
+
+
+@pytest.mark.parametrize("k", [1, 5, 8, 16, 32])
+@pytest.mark.parametrize("curve", CURVES)
+def test_knn_lidar(sfc, k, curve):
+    pts = _cloud("lidar", 40001, seed=12)
+    announce(f"knn lidar k={k} {curve}")
+    _knn_case(sfc, pts, curve, 32, k)
+
+
+def test_knn_duplicates_ties(sfc):
+    pts = _cloud("dup", 20000, seed=13)
+    for k in (4, 16, 32):
+        announce(f"knn dup k={k}")
+        _knn_case(sfc, pts, "hilbert", 8, k)
+
+
+def test_knn_external_and_padding(sfc):
+    rng = np.random.default_rng(5)
+    pts = _cloud("uniform", 30000, seed=14)
+    q = rng.uniform(-0.2, 1.2, (5003, 3)).astype(np.float32)
+    announce("knn external")
+    _knn_case(sfc, pts, "morton", 32, 16, queries=q)
+    announce("knn k > n")
+    small = _cloud("uniform", 11, seed=3)
+    _knn_case(sfc, small, "hilbert", 4, 32)
