@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 from . import _binding as B
 
-__all__ = ["encode_sfc", "build_linear_octree", "radius_search", "knn_search", "Octree",
+__all__ = ["encode_sfc", "build_linear_octree", "radius_search", "radius_count", "radius_fill", "knn_search", "Octree",
            "CURVES", "KERNELS", "library_path"]
 
 CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
@@ -179,6 +179,51 @@ def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, c
     B.check(L.radius_search(*args, _ptr(indices), int(capacity), flags, _ptr(ws), ctypes.byref(need), stream),
             "radius_search")
     return counts, offsets, indices
+
+
+def _radius_args(torch, tree, queries, kernel, r, counts, offsets):
+    if queries is not None:
+        queries = _xyz(torch, queries)
+        nq = queries.shape[0]
+    else:
+        nq = tree.n
+    return queries, nq, (ctypes.byref(tree.view), _ptr(queries), nq, _code(KERNELS, kernel), float(r),
+                         _ptr(counts), _ptr(offsets))
+
+
+def _radius_ws(torch, L, args):
+    need = ctypes.c_size_t(0)
+    B.check(L.radius_search(*args, None, 0, 0, None, ctypes.byref(need), None), "radius_search(size)")
+    return _ws(torch, need.value), need
+
+
+def radius_count(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, prune: bool = True):
+    """Count pass only: (counts int32 [nq], offsets int64 [nq + 1]); the
+    host does not synchronise."""
+    torch = _torch()
+    L = B.load()
+    nq = tree.n if queries is None else queries.shape[0]
+    counts = torch.empty(nq, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    queries, nq, args = _radius_args(torch, tree, queries, kernel, r, counts, offsets)
+    ws, need = _radius_ws(torch, L, args)
+    B.check(L.radius_search(*args, None, 0, 0 if prune else B.NO_PRUNE, _ptr(ws), ctypes.byref(need),
+                            _stream(torch)), "radius_search(count)")
+    return counts, offsets
+
+
+def radius_fill(tree: Octree, counts, offsets, indices, queries=None, kernel="sphere", r: float = 1.0,
+                prune: bool = True):
+    """Fill pass only, into `indices` (int32, capacity = its length), using
+    counts/offsets from radius_count with the same arguments."""
+    torch = _torch()
+    L = B.load()
+    queries, nq, args = _radius_args(torch, tree, queries, kernel, r, counts, offsets)
+    ws, need = _radius_ws(torch, L, args)
+    flags = B.REUSE_COUNTS | (0 if prune else B.NO_PRUNE)
+    B.check(L.radius_search(*args, _ptr(indices), indices.numel(), flags, _ptr(ws), ctypes.byref(need),
+                            _stream(torch)), "radius_search(fill)")
+    return indices
 
 
 def knn_search(tree: Octree, queries=None, k: int = 8):

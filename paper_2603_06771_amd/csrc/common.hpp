@@ -66,6 +66,16 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// readlane of unsigned values (the builtin returns int: widen through uint32_t,
+// never through int, or the value is sign-extended)
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int l) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    return (static_cast<uint64_t>(readlane_u32(static_cast<uint32_t>(v >> 32), l)) << 32) |
+           static_cast<uint64_t>(readlane_u32(static_cast<uint32_t>(v), l));
+}
+
 __device__ __forceinline__ float wave_min(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
     return v;
@@ -73,6 +83,45 @@ __device__ __forceinline__ float wave_min(float v) {
 __device__ __forceinline__ float wave_max(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
+}
+
+// Wave-uniform min / max / sum without LDS: DPP exchanges inside rows of 16
+// lanes (quad permutes, row rotations), then the four row results are read
+// with readlane.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+__device__ __forceinline__ float wave_min_u(float v) {
+    v = fminf(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = fminf(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = fminf(v, dpp_f<0x124>(v));  // row_ror:4
+    v = fminf(v, dpp_f<0x128>(v));  // row_ror:8
+    const int x = __float_as_int(v);
+    return fminf(fminf(__int_as_float(__builtin_amdgcn_readlane(x, 0)), __int_as_float(__builtin_amdgcn_readlane(x, 16))),
+                 fminf(__int_as_float(__builtin_amdgcn_readlane(x, 32)), __int_as_float(__builtin_amdgcn_readlane(x, 48))));
+}
+__device__ __forceinline__ float wave_max_u(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));
+    v = fmaxf(v, dpp_f<0x4E>(v));
+    v = fmaxf(v, dpp_f<0x124>(v));
+    v = fmaxf(v, dpp_f<0x128>(v));
+    const int x = __float_as_int(v);
+    return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(x, 0)), __int_as_float(__builtin_amdgcn_readlane(x, 16))),
+                 fmaxf(__int_as_float(__builtin_amdgcn_readlane(x, 32)), __int_as_float(__builtin_amdgcn_readlane(x, 48))));
+}
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+    int x = static_cast<int>(v);
+    x += dpp_i<0xB1>(x);
+    x += dpp_i<0x4E>(x);
+    x += dpp_i<0x124>(x);
+    x += dpp_i<0x128>(x);
+    const uint32_t u = static_cast<uint32_t>(x);
+    return readlane_u32(u, 0) + readlane_u32(u, 16) + readlane_u32(u, 32) + readlane_u32(u, 48);
 }
 
 template <typename T>

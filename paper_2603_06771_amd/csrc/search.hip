@@ -37,11 +37,29 @@ namespace sfc {
 
 namespace {
 
-constexpr int kStack = 1024;
-constexpr int kCand = 128;
-constexpr int kStage = 512;
-constexpr int kRowCap = 64;
-constexpr int kChunk = 32;
+// Tile parameters (overridable at build time for tuning sweeps).
+#ifndef SFC_STACK
+#define SFC_STACK 256
+#endif
+#ifndef SFC_CAND
+#define SFC_CAND 128
+#endif
+#ifndef SFC_STAGE
+#define SFC_STAGE 128
+#endif
+#ifndef SFC_ROWCAP
+#define SFC_ROWCAP 32
+#endif
+#ifndef SFC_CHUNK
+#define SFC_CHUNK 16
+#endif
+constexpr int kStack = SFC_STACK;     // traversal stack entries
+constexpr int kCand = SFC_CAND;       // candidate nodes held before a sweep
+constexpr int kStage = SFC_STAGE;     // points staged per round
+constexpr int kRowCap = SFC_ROWCAP;   // fill: staged output entries per query
+constexpr int kChunk = SFC_CHUNK;     // fill: points swept between flush checks
+constexpr int kSegMax = 8;            // query segments per wave
+static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0, "tile parameters");
 
 template <int KERNEL>
 __device__ __forceinline__ bool point_hit(const float4 &p, float qx, float qy, float qz, float r, float r2) {
@@ -147,27 +165,75 @@ __device__ __forceinline__ Query load_query(const float *queries, const float4 *
     return q;
 }
 
-__device__ __forceinline__ void group_box(const Query &q, float *glo, float *ghi) {
-    glo[0] = wave_min(q.valid ? q.x : INFINITY);
-    glo[1] = wave_min(q.valid ? q.y : INFINITY);
-    glo[2] = wave_min(q.valid ? q.z : INFINITY);
-    ghi[0] = wave_max(q.valid ? q.x : -INFINITY);
-    ghi[1] = wave_max(q.valid ? q.y : -INFINITY);
-    ghi[2] = wave_max(q.valid ? q.z : -INFINITY);
-}
-
 // Shared LDS of one wave: traversal stack, candidate nodes, staged points.
 struct WaveLds {
     int stack[kStack];
     sfc_node cand[kCand];
     float4 pts[kStage];
-    uint32_t cstart[65];
+    uint8_t owner[kStage];   // candidate (within the batch) of each staged point
+    uint32_t cincl[kWave];   // inclusive prefix of staged sizes of the batch
+    float seg[kSegMax][6];   // boxes of the query segments
 };
 
+// Splits the wave's 64 queries into at most kSegMax runs of consecutive
+// queries, cutting where two consecutive queries are more than `jump` apart
+// (the largest such steps first).  A space-filling curve visits empty space
+// between occupied regions, so consecutive points can be far apart; one box
+// over such a group would cover the whole gap.  Writes the run boxes to
+// L.seg and returns their number.
+template <typename Lds>
+__device__ __forceinline__ int make_segments(Lds &L, const Query &q, float jump, int *sid_out) {
+    const int lane = lane_id();
+    const float px = __shfl_up(q.x, 1), py = __shfl_up(q.y, 1), pz = __shfl_up(q.z, 1);
+    const int pv = __shfl_up(q.valid ? 1 : 0, 1);
+    float step = 0.0f;
+    if (lane > 0 && q.valid && pv) step = fmaxf(fabsf(q.x - px), fmaxf(fabsf(q.y - py), fabsf(q.z - pz)));
+    const bool brk = step > jump;
+    uint64_t bm = ballot(brk);
+    if (__popcll(bm) > kSegMax - 1) {
+        uint64_t keep = 0;
+        float sv = brk ? step : -1.0f;
+        for (int i = 0; i < kSegMax - 1; ++i) {
+            const float m = wave_max_u(sv);
+            const uint64_t w = ballot(brk && sv == m);
+            const int l = __ffsll(static_cast<long long>(w)) - 1;
+            keep |= 1ull << l;
+            if (lane == l) sv = -1.0f;
+        }
+        bm = keep;
+    }
+    const int sid = __popcll(bm & ((2ull << lane) - 1ull));
+    const int nseg = __popcll(bm) + 1;
+    for (int s = 0; s < nseg; ++s) {
+        const bool in = q.valid && sid == s;
+        const float b0 = wave_min_u(in ? q.x : INFINITY), b1 = wave_min_u(in ? q.y : INFINITY);
+        const float b2 = wave_min_u(in ? q.z : INFINITY), b3 = wave_max_u(in ? q.x : -INFINITY);
+        const float b4 = wave_max_u(in ? q.y : -INFINITY), b5 = wave_max_u(in ? q.z : -INFINITY);
+        if (lane == 0) {
+            L.seg[s][0] = b0;
+            L.seg[s][1] = b1;
+            L.seg[s][2] = b2;
+            L.seg[s][3] = b3;
+            L.seg[s][4] = b4;
+            L.seg[s][5] = b5;
+        }
+    }
+    __syncthreads();
+    if (sid_out) *sid_out = sid;
+    return nseg;
+}
+
+template <int KERNEL, typename Lds>
+__device__ __forceinline__ bool segments_may_hit(const Lds &L, int nseg, const sfc_node &nd, float r, float r2) {
+    bool hit = false;
+    for (int s = 0; s < nseg; ++s) hit = hit || group_may_hit<KERNEL>(nd, &L.seg[s][0], &L.seg[s][3], r, r2);
+    return hit;
+}
+
 // Walks the tree; each time the candidate list fills up (or the walk ends)
-// calls sweep(ncand).  ACCEPT(node) decides whether the wave keeps a node.
-template <typename Accept, typename Sweep>
-__device__ __forceinline__ void traverse(WaveLds &L, const sfc_node *__restrict__ nodes,
+// calls sweep(ncand).  accept(node) decides whether the wave keeps a node.
+template <typename Lds, typename Accept, typename Sweep>
+__device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ nodes,
                                          const int32_t *__restrict__ child, Accept accept, Sweep sweep) {
     const int lane = lane_id();
     if (lane == 0) L.stack[0] = 0;
@@ -213,65 +279,50 @@ __device__ __forceinline__ void traverse(WaveLds &L, const sfc_node *__restrict_
     }
 }
 
-// Stages candidates [c0, c0 + nb) (their points, total <= kStage) into L.pts;
-// L.cstart[i] is the first staged slot of candidate c0 + i.
-__device__ __forceinline__ void stage_points(WaveLds &L, const float4 *__restrict__ pts, int c0, int nb,
-                                             uint32_t total) {
-    const int lane = lane_id();
-    for (uint32_t p = lane; p < total; p += kWave) {
-        int lo = 0, hi = nb - 1;  // last candidate whose start <= p
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.cstart[mid] <= p)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        L.pts[p] = pts[L.cand[c0 + lo].begin + (p - L.cstart[lo])];
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+    uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+        lo |= __shfl_xor(lo, o);
+        hi |= __shfl_xor(hi, o);
     }
-    __syncthreads();
+    return (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi))) << 32) |
+           static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo)));
 }
 
-// Batches the candidate list into stageable groups and calls
-// visit(node, staged_points, count) for every candidate.  A candidate larger
-// than the staging area is visited in slices.
-template <typename Visit>
-__device__ __forceinline__ void sweep_candidates(WaveLds &L, const float4 *__restrict__ pts, int ncand, Visit visit) {
+// Stages the points of the batch candidates [c0, c0 + m) selected by `need`
+// (bit i: candidate c0 + i), in candidate order, kStage points per round, and
+// for every round calls body(count): L.pts[0..count) are the points and
+// L.owner[] their candidate within the batch.  A candidate larger than the
+// staging area spans several rounds.
+template <typename Body>
+__device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
+                                             Body body) {
     const int lane = lane_id();
-    int c0 = 0;
-    while (c0 < ncand) {
-        const int m = min(kWave, ncand - c0);
-        uint32_t sz = 0;
-        if (lane < m) sz = L.cand[c0 + lane].end - L.cand[c0 + lane].begin;
-        const uint32_t incl = wave_inclusive_sum(sz);
-        const int nb = __popcll(ballot(lane < m && incl <= static_cast<uint32_t>(kStage)));
-        if (nb == 0) {
-            // one candidate bigger than the staging area: slice it
-            const sfc_node nd = L.cand[c0];
-            for (uint32_t s0 = nd.begin; s0 < nd.end; s0 += kStage) {
-                const uint32_t len = min(static_cast<uint32_t>(kStage), nd.end - s0);
-                __syncthreads();
-                for (uint32_t p = lane; p < len; p += kWave) L.pts[p] = pts[s0 + p];
-                __syncthreads();
-                sfc_node part = nd;
-                part.begin = s0;
-                part.end = s0 + len;
-                visit(part, L.pts, len);
+    uint32_t sz = 0;
+    if (lane < m && ((need >> lane) & 1ull)) sz = L.cand[c0 + lane].end - L.cand[c0 + lane].begin;
+    const uint32_t incl = wave_inclusive_sum(sz);
+    L.cincl[lane] = incl;
+    const uint32_t total = __shfl(incl, kWave - 1);
+    __syncthreads();
+    for (uint32_t done = 0; done < total; done += kStage) {
+        const uint32_t cnt = min(static_cast<uint32_t>(kStage), total - done);
+        for (uint32_t t = lane; t < cnt; t += kWave) {
+            const uint32_t p = done + t;
+            int lo = 0, hi = m - 1;  // first candidate whose inclusive end exceeds p
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (L.cincl[mid] > p)
+                    hi = mid;
+                else
+                    lo = mid + 1;
             }
-            __syncthreads();
-            c0 += 1;
-            continue;
-        }
-        if (lane < nb) L.cstart[lane] = incl - sz;
-        const uint32_t total = __shfl(incl, nb - 1);
-        __syncthreads();
-        stage_points(L, pts, c0, nb, total);
-        for (int o = 0; o < nb; ++o) {
-            const sfc_node nd = L.cand[c0 + o];
-            visit(nd, L.pts + L.cstart[o], nd.end - nd.begin);
+            const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
+            L.pts[t] = pts[L.cand[c0 + lo].begin + (p - first)];
+            L.owner[t] = static_cast<uint8_t>(lo);
         }
         __syncthreads();
-        c0 += nb;
+        body(cnt);
+        __syncthreads();
     }
 }
 
@@ -290,87 +341,245 @@ struct RadiusArgs {
     uint64_t capacity;
 };
 
+// Radius search.  Every candidate node is classified against the box of
+// every query segment (exactly, by the monotonicity argument): disjoint from
+// every query of the segment, contained for every one of them, or mixed.
+// Nodes that are mixed for some segment are staged in LDS and swept: every
+// lane tests its own query against every staged point (a lane for which the
+// node is contained gets "true" for each of its points, by the same
+// argument, so no per-lane bookkeeping is needed).  Nodes contained for a
+// segment and mixed for none are counted without touching their points.
+struct RadLds {
+    int stack[kStack];
+    sfc_node cand[kCand];
+    float4 pts[kStage];
+    uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
+    uint32_t clen[kWave];   // sizes of the batch candidates
+    float seg[kSegMax][6];
+};
+
+struct FillLds : RadLds {
+    uint32_t rows[kWave * (kRowCap + 1)];  // per-query output staging
+};
+
+// largest |fp32 difference| between a coordinate of [lo, hi] and one of [glo, ghi]
+__device__ __forceinline__ float far_gap(float lo, float hi, float glo, float ghi) {
+    return fmaxf(fabsf(fsub(lo, ghi)), fabsf(fsub(hi, glo)));
+}
+
+// 0: no point of the node is a neighbour of any query in the box [glo, ghi];
+// 1: every point is a neighbour of every such query; 2: mixed.
+template <int KERNEL>
+__device__ __forceinline__ int classify_box(const sfc_node &b, const float *glo, const float *ghi, float r,
+                                            float r2) {
+    if (!group_may_hit<KERNEL>(b, glo, ghi, r, r2)) return 0;
+    const float fx = far_gap(b.lo[0], b.hi[0], glo[0], ghi[0]);
+    const float fy = far_gap(b.lo[1], b.hi[1], glo[1], ghi[1]);
+    if constexpr (KERNEL == SFC_SPHERE) {
+        const float fz = far_gap(b.lo[2], b.hi[2], glo[2], ghi[2]);
+        return fadd(fadd(fmul(fx, fx), fmul(fy, fy)), fmul(fz, fz)) < r2 ? 1 : 2;
+    } else if constexpr (KERNEL == SFC_CIRCLE) {
+        return fadd(fmul(fx, fx), fmul(fy, fy)) < r2 ? 1 : 2;
+    } else if constexpr (KERNEL == SFC_CUBE) {
+        const float fz = far_gap(b.lo[2], b.hi[2], glo[2], ghi[2]);
+        return (fx < r && fy < r && fz < r) ? 1 : 2;
+    } else {
+        return (fx < r && fy < r) ? 1 : 2;
+    }
+}
+
+// Classifies the batch candidates [c0, c0 + m) (lane = candidate) against
+// every segment box.  Stores the candidate sizes in L.clen and returns the
+// lane's own; *mixed / *touched: candidates mixed / not disjoint for some
+// segment; *full: candidates contained for the calling lane's segment.
+template <int KERNEL, typename Lds>
+__device__ __forceinline__ uint32_t classify_segments(Lds &L, int c0, int m, int nseg, int sid, float r, float r2,
+                                                      bool prune, uint64_t *mixed, uint64_t *touched, uint64_t *full) {
+    const int lane = lane_id();
+    const bool have = lane < m;
+    sfc_node nd;
+    if (have) nd = L.cand[c0 + lane];
+    const uint32_t len = have ? nd.end - nd.begin : 0u;
+    L.clen[lane] = len;
+    uint64_t mx = 0, tc = 0, fm = 0;
+    for (int s = 0; s < nseg; ++s) {
+        int cls = have ? classify_box<KERNEL>(nd, &L.seg[s][0], &L.seg[s][3], r, r2) : 0;
+        if (cls == 1 && !prune) cls = 2;
+        mx |= ballot(cls == 2);
+        tc |= ballot(cls != 0);
+        const uint64_t f = ballot(cls == 1);
+        if (sid == s) fm = f;
+    }
+    *mixed = mx;
+    *touched = tc;
+    *full = fm;
+    __syncthreads();
+    return len;
+}
+
+// Stages the points of the batch candidates [c0, c0 + m) selected by `need`
+// (bit i: candidate c0 + i), in candidate order, kStage points per round, and
+// calls body(count) with L.pts[0..count) filled.
+template <typename Lds, typename Body>
+__device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
+                                            uint32_t len, Body body) {
+    const int lane = lane_id();
+    const uint32_t incl = wave_inclusive_sum(((need >> lane) & 1ull) ? len : 0u);
+    L.cincl[lane] = incl;
+    const uint32_t total = __shfl(incl, kWave - 1);
+    __syncthreads();
+    for (uint32_t done = 0; done < total; done += kStage) {
+        const uint32_t cnt = min(static_cast<uint32_t>(kStage), total - done);
+        for (uint32_t t = lane; t < cnt; t += kWave) {
+            const uint32_t p = done + t;
+            int lo = 0, hi = m - 1;  // first candidate whose inclusive end exceeds p
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (L.cincl[mid] > p)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
+            L.pts[t] = pts[L.cand[c0 + lo].begin + (p - first)];
+        }
+        __syncthreads();
+        body(cnt);
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 template <int KERNEL>
 __global__ __launch_bounds__(64) void k_radius_count(RadiusArgs a) {
-    __shared__ WaveLds L;
+    __shared__ RadLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
-    const int64_t row = g * kWave + lane_id();
+    const int lane = lane_id();
+    const int64_t row = g * kWave + lane;
     const Query q = load_query(a.queries, a.pts, row, a.nq);
-    float glo[3], ghi[3];
-    group_box(q, glo, ghi);
     const float r = a.r, r2 = fmul(r, r);
     const bool prune = !(a.flags & SFC_NO_PRUNE);
+    int sid = 0;
+    const int nseg = make_segments(L, q, 2.0f * r, &sid);
     uint32_t cnt = 0;
-    auto accept = [&](const sfc_node &nd) { return group_may_hit<KERNEL>(nd, glo, ghi, r, r2); };
-    auto visit = [&](const sfc_node &nd, const float4 *sp, uint32_t len) {
-        int cls = q.valid ? classify<KERNEL>(nd, q.x, q.y, q.z, r, r2) : 0;
-        if (cls == 1 && !prune) cls = 2;
-        if (cls == 1) cnt += len;
-        if (ballot(cls == 2)) {
-            const bool test = cls == 2;
-            for (uint32_t j = 0; j < len; ++j) cnt += (test && point_hit<KERNEL>(sp[j], q.x, q.y, q.z, r, r2)) ? 1u : 0u;
+    auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
+    auto sweep = [&](int ncand) {
+        for (int c0 = 0; c0 < ncand; c0 += kWave) {
+            const int m = min(kWave, ncand - c0);
+            uint64_t mixed, touched, full;
+            const uint32_t len = classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+            // contained for my segment and not swept: count the whole node
+            for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
+            if (!mixed) continue;
+            stage_union(L, a.pts, c0, m, mixed, len, [&](uint32_t n) {
+                uint32_t t = 0;
+                for (; t + 4 <= n; t += 4) {
+                    const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
+                    cnt += point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                    cnt += point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                    cnt += point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                    cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                }
+                for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
+            });
         }
     };
-    auto sweep = [&](int ncand) { sweep_candidates(L, a.pts, ncand, visit); };
     traverse(L, a.nodes, a.child, accept, sweep);
     if (q.valid) a.counts[row] = cnt;
 }
 
 template <int KERNEL>
 __global__ __launch_bounds__(64) void k_radius_fill(RadiusArgs a) {
-    __shared__ WaveLds L;
-    __shared__ uint32_t s_rows[kWave * (kRowCap + 1)];
+    __shared__ FillLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq] > a.capacity) return;  // caller's buffer too small: write nothing
     const int lane = lane_id();
     const int64_t row = g * kWave + lane;
     const Query q = load_query(a.queries, a.pts, row, a.nq);
-    float glo[3], ghi[3];
-    group_box(q, glo, ghi);
     const float r = a.r, r2 = fmul(r, r);
     const bool prune = !(a.flags & SFC_NO_PRUNE);
+    int sid = 0;
+    const int nseg = make_segments(L, q, 2.0f * r, &sid);
+    // an invalid lane owns an empty row and never appends
     uint64_t gpos = q.valid ? a.offsets[row] : 0;
-    const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;  // never write past the counted row
-    int nb = 0;
-    uint32_t *myrow = s_rows + lane * (kRowCap + 1);
+    const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;
+    uint32_t nb = 0;
+    uint32_t *myrow = L.rows + lane * (kRowCap + 1);
     uint32_t *out = a.indices;
+    const int half = lane >> 5, hl = lane & 31;
 
-    // write out every row holding more than `limit` staged entries
-    auto flush = [&](int limit) {
-        uint64_t m = ballot(nb > limit);
-        while (m) {
-            const int l = __ffsll(static_cast<long long>(m)) - 1;
-            m &= m - 1;
-            const int cl = __shfl(nb, l);
-            const uint64_t base = __shfl(gpos, l);
-            const uint64_t end = __shfl(gend, l);
-            if (lane < cl && base + lane < end) out[base + lane] = s_rows[l * (kRowCap + 1) + lane];
-            if (lane == l) {
-                gpos += static_cast<uint64_t>(nb);
-                nb = 0;
+    // Writes out every row holding more than `limit` entries, two rows per
+    // step (one per half wave, 32 consecutive slots each: coalesced stores).
+    // Row cursors stay in their lanes' registers and are read with readlane.
+    auto flush = [&](uint32_t limit) {
+        uint64_t fm = ballot(nb > limit);
+        if (!fm) return;
+        __syncthreads();
+        while (fm) {
+            const int l0 = __ffsll(static_cast<long long>(fm)) - 1;
+            fm &= fm - 1;
+            int l1 = l0;
+            bool two = false;
+            if (fm) {
+                l1 = __ffsll(static_cast<long long>(fm)) - 1;
+                fm &= fm - 1;
+                two = true;
             }
+            const uint32_t n0 = readlane_u32(nb, l0), n1 = two ? readlane_u32(nb, l1) : 0u;
+            const uint64_t b0 = readlane_u64(gpos, l0), b1 = readlane_u64(gpos, l1);
+            const uint64_t e0 = readlane_u64(gend, l0), e1 = readlane_u64(gend, l1);
+            const int l = half ? l1 : l0;
+            const uint32_t cl = half ? n1 : n0;
+            const uint64_t at = (half ? b1 : b0) + static_cast<uint64_t>(hl);
+            if (static_cast<uint32_t>(hl) < cl && at < (half ? e1 : e0)) out[at] = L.rows[l * (kRowCap + 1) + hl];
+        }
+        if (nb > limit) {
+            gpos += nb;
+            nb = 0;
+        }
+        __syncthreads();
+    };
+    auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
+    auto sweep = [&](int ncand) {
+        for (int c0 = 0; c0 < ncand; c0 += kWave) {
+            const int m = min(kWave, ncand - c0);
+            uint64_t mixed, touched, full;
+            const uint32_t len = classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+            if (!touched) continue;
+            stage_union(L, a.pts, c0, m, touched, len, [&](uint32_t n) {
+                for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
+                    flush(kRowCap - kChunk);
+                    const uint32_t te = min(n, t0 + kChunk);
+                    uint32_t t = t0;
+                    for (; t + 4 <= te; t += 4) {
+                        const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
+                        const bool h0 = point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) & q.valid;
+                        const bool h1 = point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) & q.valid;
+                        const bool h2 = point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) & q.valid;
+                        const bool h3 = point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) & q.valid;
+                        // each slot is overwritten unless it holds a hit
+                        myrow[nb] = __float_as_uint(p0.w);
+                        nb += h0 ? 1u : 0u;
+                        myrow[nb] = __float_as_uint(p1.w);
+                        nb += h1 ? 1u : 0u;
+                        myrow[nb] = __float_as_uint(p2.w);
+                        nb += h2 ? 1u : 0u;
+                        myrow[nb] = __float_as_uint(p3.w);
+                        nb += h3 ? 1u : 0u;
+                    }
+                    for (; t < te; ++t) {
+                        const float4 p = L.pts[t];
+                        const bool h = point_hit<KERNEL>(p, q.x, q.y, q.z, r, r2) & q.valid;
+                        myrow[nb] = __float_as_uint(p.w);
+                        nb += h ? 1u : 0u;
+                    }
+                }
+            });
         }
     };
-    auto accept = [&](const sfc_node &nd) { return group_may_hit<KERNEL>(nd, glo, ghi, r, r2); };
-    auto visit = [&](const sfc_node &nd, const float4 *sp, uint32_t len) {
-        int cls = q.valid ? classify<KERNEL>(nd, q.x, q.y, q.z, r, r2) : 0;
-        if (cls == 1 && !prune) cls = 2;
-        if (!ballot(cls != 0)) return;
-        for (uint32_t j0 = 0; j0 < len; j0 += kChunk) {
-            const uint32_t jn = min(len - j0, static_cast<uint32_t>(kChunk));
-            flush(kRowCap - static_cast<int>(jn));
-            for (uint32_t j = j0; j < j0 + jn; ++j) {
-                const float4 p = sp[j];
-                const bool h = cls == 1 || (cls == 2 && point_hit<KERNEL>(p, q.x, q.y, q.z, r, r2));
-                if (h) myrow[nb++] = __float_as_uint(p.w);
-            }
-        }
-    };
-    auto sweep = [&](int ncand) { sweep_candidates(L, a.pts, ncand, visit); };
     traverse(L, a.nodes, a.child, accept, sweep);
     flush(0);
 }
@@ -443,44 +652,53 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
         tau = 0.0f;
         for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(a.pts[s + i], q.x, q.y, q.z));
     }
-    float glo[3], ghi[3];
-    group_box(q, glo, ghi);
     const float R2 = wave_max(q.valid ? tau : 0.0f);
     const float R2open = R2 < INFINITY ? nextafterf(R2, INFINITY) : INFINITY;
+    const int nseg = make_segments(L, q, R2 < INFINITY ? 2.0f * sqrtf(R2) : INFINITY, nullptr);
 
     int64_t best[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) best[i] = i < k ? kPad : int64_t(-1);
 
-    auto accept = [&](const sfc_node &nd) { return group_may_hit<SFC_SPHERE>(nd, glo, ghi, 0.0f, R2open); };
-    auto visit = [&](const sfc_node &nd, const float4 *sp, uint32_t len) {
-        float thr = tau;
-        const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
-        if (kth < thr) thr = kth;
-        bool live = false;
-        if (q.valid) {
-            float nx, fx, ny, fy, nz, fz;
-            axis_range(nd.lo[0], nd.hi[0], q.x, nx, fx);
-            axis_range(nd.lo[1], nd.hi[1], q.y, ny, fy);
-            axis_range(nd.lo[2], nd.hi[2], q.z, nz, fz);
-            const float near2 = fadd(fadd(fmul(nx, nx), fmul(ny, ny)), fmul(nz, nz));
-            live = !(near2 > thr);  // equality kept: an equal d2 with a smaller index may enter
-        }
-        if (!ballot(live)) return;
-        for (uint32_t j = 0; j < len; ++j) {
-            const float4 p = sp[j];
-            const float d = dist2(p, q.x, q.y, q.z);
-            const int64_t x = pack(d, __float_as_uint(p.w));
-            if (live && d <= tau && x < best[0]) {
-#pragma unroll
-                for (int i = 0; i < KMAX; ++i) {
-                    const int64_t nxt = (i + 1 < KMAX) ? best[i + 1] : int64_t(-1);
-                    best[i] = nxt > x ? nxt : (best[i] > x ? x : best[i]);
+    auto accept = [&](const sfc_node &nd) { return segments_may_hit<SFC_SPHERE>(L, nseg, nd, 0.0f, R2open); };
+    auto sweep = [&](int ncand) {
+        for (int c0 = 0; c0 < ncand; c0 += kWave) {
+            const int m = min(kWave, ncand - c0);
+            float thr = tau;
+            const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
+            if (kth < thr) thr = kth;
+            uint64_t lm = 0;
+            if (q.valid) {
+                for (int i = 0; i < m; ++i) {
+                    const sfc_node nd = L.cand[c0 + i];
+                    float nx, fx, ny, fy, nz, fz;
+                    axis_range(nd.lo[0], nd.hi[0], q.x, nx, fx);
+                    axis_range(nd.lo[1], nd.hi[1], q.y, ny, fy);
+                    axis_range(nd.lo[2], nd.hi[2], q.z, nz, fz);
+                    const float near2 = fadd(fadd(fmul(nx, nx), fmul(ny, ny)), fmul(nz, nz));
+                    // equality kept: an equal d2 with a smaller index may still enter
+                    if (!(near2 > thr)) lm |= 1ull << i;
                 }
             }
+            const uint64_t need = wave_or(lm);
+            if (!need) continue;
+            stage_rounds(L, a.pts, c0, m, need, [&](uint32_t n) {
+                for (uint32_t t = 0; t < n; ++t) {
+                    const float4 p = L.pts[t];
+                    const uint32_t o = L.owner[t];
+                    const float d = dist2(p, q.x, q.y, q.z);
+                    const int64_t x = pack(d, __float_as_uint(p.w));
+                    if (((lm >> o) & 1ull) && d <= tau && x < best[0]) {
+#pragma unroll
+                        for (int i = 0; i < KMAX; ++i) {
+                            const int64_t nxt = (i + 1 < KMAX) ? best[i + 1] : int64_t(-1);
+                            best[i] = nxt > x ? nxt : (best[i] > x ? x : best[i]);
+                        }
+                    }
+                }
+            });
         }
     };
-    auto sweep = [&](int ncand) { sweep_candidates(L, a.pts, ncand, visit); };
     traverse(L, a.nodes, a.child, accept, sweep);
     if (q.valid) {
         uint32_t *oi = a.idx + row * k;
