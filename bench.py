@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=100_000, help="queries per (kernel, r) for the oracle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     return ap.parse_args()
 
 
@@ -97,6 +99,12 @@ def main():
     print(f"[bench] generated {pts.shape[0]} points in {gen_s:.1f} s", file=sys.stderr, flush=True)
     xyz = torch.from_numpy(pts).cuda()
     n = pts.shape[0]
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
 
     # size the output once: the largest neighbour total over the workload
@@ -196,6 +204,17 @@ def main():
         detail[f"{c}/{k}/r={r}"] = {"mu": totals[cb] / n, "fill_ms": round(ms, 4),
                                     "fill_GBps": round(b / ms / 1e6, 1)}
     achieved = tot_bytes / tot_ms / 1e6  # GB/s
+    # measured HBM bytes per fill launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid only
+    # while the kernel source is the one the counters were taken on
+    traffic = None
+    try:
+        from paper_2603_06771_amd import rocprof_summary
+        rec = json.load(open(os.path.join(ROOT, "profiles", "k_radius_fill_lidar10M_traffic.json")))
+        src = os.path.join(ROOT, "paper_2603_06771_amd", "csrc", "search.hip")
+        if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 16 and n == 10_000_000:
+            traffic = rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
     queries_per_step = len(combos) * n
     value = queries_per_step / (ms_per_step / 1e3)
 
@@ -216,7 +235,8 @@ def main():
                    "kernels": list(KERNELS), "radii_m": list(RADII), "leaf_size": args.leaf,
                    "queries_per_step": queries_per_step, "builds_per_step": len(CURVES)},
         "roofline": {"bound": "hbm", "kernel": "k_radius_fill", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": tot_bytes / len(combos)},
         "build_ms": {c: round(v, 3) for c, v in build_ms.items()},
         "tree": {c: {"n_nodes": infos[c]["n_nodes"], "n_leaves": infos[c]["n_leaves"], "depth": infos[c]["depth"]}
                  for c in CURVES},

@@ -1,0 +1,98 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
+
+    python -m paper_2603_06771_amd.rocprof_summary stats <kernel_stats.csv>
+    python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
+        <write_counter_collection.csv> [kernel-substring]
+
+`traffic` reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the matching
+kernel, scaled by what the same counters read for the plain device copy of
+known size in the same run (the largest elementwise copy dispatch).
+"""
+from __future__ import annotations
+
+import csv
+import statistics
+import sys
+
+COPY_BYTES = 2 * (64 << 20) * 4  # 256 MiB read + 256 MiB written by the calibration copy
+
+
+def stats(path: str, top: int = 25) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in rows[:top]:
+        out.append(f"{r['Name'][:70]:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+    return "\n".join(out)
+
+
+def _per_dispatch(path: str, counter: str):
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic(fetch_path: str, write_path: str, kernel: str = "k_radius_fill", min_kib: float = 1024.0) -> str:
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE of `kernel` (dispatches reading or
+    writing at least min_kib), scaled by the calibration copy's readings."""
+    fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
+    write = _per_dispatch(write_path, "WRITE_SIZE")
+
+    def copy_ref(rows):
+        vals = [v for _, k, v in rows if "copyBuffer" in k]
+        return max(vals) if vals else None
+
+    fc, wc = copy_ref(fetch), copy_ref(write)
+    half = COPY_BYTES // 2
+    ffac = half / (fc * 1024) if fc else 1.0
+    wfac = half / (wc * 1024) if wc else 1.0
+    lines = [f"calibration: plain device copy of {half} B (__amd_rocclr_copyBuffer)",
+             f"  FETCH_SIZE {fc} KiB -> scale {ffac:.4f};  WRITE_SIZE {wc} KiB -> scale {wfac:.4f}",
+             f"{'dispatch':>8s} {'fetch_KiB':>12s} {'write_KiB':>12s} {'fetch_B_scaled':>15s} {'write_B_scaled':>15s}  kernel"]
+    wmap = {d: v for d, k, v in write if kernel in k}
+    for d, k, v in fetch:
+        if kernel not in k:
+            continue
+        w = wmap.get(d, float("nan"))
+        if max(v, w if w == w else 0.0) < min_kib:
+            continue
+        lines.append(f"{d:8d} {v:12.0f} {w:12.0f} {v * 1024 * ffac:15.4g} {w * 1024 * wfac:15.4g}  {k[:60]}")
+    return "\n".join(lines)
+
+
+def source_sha(path: str) -> str:
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, min_kib: float = 1024.0) -> dict:
+    """Mean scaled HBM bytes per launch of `kernel`, tagged with the hash of
+    the kernel's source file (a reader uses it only while the hash matches)."""
+    fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
+    write = {d: v for d, k, v in _per_dispatch(write_path, "WRITE_SIZE") if kernel in k}
+    fc = max(v for _, k, v in fetch if "copyBuffer" in k)
+    wc = max(v for _, k, v in _per_dispatch(write_path, "WRITE_SIZE") if "copyBuffer" in k)
+    half = COPY_BYTES // 2
+    ffac, wfac = half / (fc * 1024), half / (wc * 1024)
+    f_b, w_b = [], []
+    for d, k, v in fetch:
+        if kernel in k and d in write and max(v, write[d]) >= min_kib:
+            f_b.append(v * 1024 * ffac)
+            w_b.append(write[d] * 1024 * wfac)
+    return {"kernel": kernel, "source_sha": source_sha(source), "launches": len(f_b),
+            "fetch_bytes_per_launch": statistics.mean(f_b), "write_bytes_per_launch": statistics.mean(w_b),
+            "bytes_per_launch": statistics.mean(f_b) + statistics.mean(w_b),
+            "fetch_scale": ffac, "write_scale": wfac}
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        print(stats(sys.argv[2]))
+    elif sys.argv[1] == "record":
+        import json
+        print(json.dumps(traffic_record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5]), indent=1))
+    else:
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "k_radius_fill"))

@@ -1,0 +1,105 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/sfcoct.h declares, and its host-only paths (size queries, argument
+validation) behave as documented.  No call here launches GPU work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2603_06771_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfcoct.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2603_06771_amd import build
+        build.build()
+    return B.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_lists_the_entry_points():
+    names = _declared()
+    for n in ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
+              "sfc_last_error", "sfc_version"):
+        assert n in names
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.sfc_version()
+
+
+def test_octree_bytes_bound(lib):
+    b = ctypes.c_size_t(0)
+    assert lib.octree_bytes(0, 8, 21, ctypes.byref(b)) == B.SFC_OK and b.value > 0
+    assert lib.octree_bytes(10_000_000, 16, 21, ctypes.byref(b)) == B.SFC_OK
+    small = b.value
+    assert lib.octree_bytes(10_000_000, 128, 21, ctypes.byref(b)) == B.SFC_OK
+    assert b.value < small
+    # invalid arguments
+    assert lib.octree_bytes(-1, 8, 21, ctypes.byref(b)) == B.SFC_EINVAL
+    assert lib.octree_bytes(10, 0, 21, ctypes.byref(b)) == B.SFC_EINVAL
+    assert lib.octree_bytes(10, 8, 22, ctypes.byref(b)) == B.SFC_EINVAL
+    assert b"invalid" in lib.sfc_last_error()
+    # node bound beyond int32 is refused, not overflowed
+    assert lib.octree_bytes(0xFFFFFFFF, 1, 21, ctypes.byref(b)) == B.SFC_ENOTSUP
+
+
+def test_workspace_size_queries_do_not_launch(lib):
+    need = ctypes.c_size_t(0)
+    # encode: ws == NULL only reports the size
+    assert lib.encode_sfc(None, 0, 0, 21, None, None, None, ctypes.byref(need), None) == B.SFC_OK
+    assert need.value >= 256
+    # invalid curve / bits are rejected before anything is enqueued
+    fake = ctypes.c_void_p(256)
+    rc = lib.encode_sfc(fake, 10, 7, 21, fake, fake, fake, ctypes.byref(ctypes.c_size_t(1 << 20)), None)
+    assert rc == B.SFC_EINVAL
+    rc = lib.encode_sfc(fake, 10, 0, 0, fake, fake, fake, ctypes.byref(ctypes.c_size_t(1 << 20)), None)
+    assert rc == B.SFC_EINVAL
+    # too small a workspace is reported as such
+    rc = lib.encode_sfc(fake, 10, 0, 21, fake, fake, fake, ctypes.byref(ctypes.c_size_t(16)), None)
+    assert rc == B.SFC_EWORKSPACE
+    # build: size query, then invalid leaf size
+    assert lib.build_linear_octree(None, 1000, 1, 21, 16, None, 0, None, None, ctypes.byref(need), None) == B.SFC_OK
+    assert need.value > 0
+    assert lib.build_linear_octree(None, 1000, 1, 21, 0, None, 0, None, None, ctypes.byref(need), None) \
+        == B.SFC_EINVAL
+
+
+def test_search_argument_validation(lib):
+    need = ctypes.c_size_t(0)
+    view = B.SfcOctree()  # all-null view: rejected
+    rc = lib.radius_search(ctypes.byref(view), None, 0, 0, 1.0, None, None, None, 0, 0, None, ctypes.byref(need),
+                           None)
+    assert rc == B.SFC_EINVAL
+    rc = lib.knn_search(ctypes.byref(view), None, 0, 8, None, None, None, ctypes.byref(need), None)
+    assert rc == B.SFC_EINVAL
+    # a syntactically valid view with bad parameters
+    view.nodes = view.child = view.points = view.keys = view.frame = 256
+    view.n = 10
+    fake = ctypes.c_void_p(256)
+    assert lib.radius_search(ctypes.byref(view), None, 10, 9, 1.0, fake, fake, None, 0, 0, None,
+                             ctypes.byref(need), None) == B.SFC_EINVAL  # kernel out of range
+    assert lib.radius_search(ctypes.byref(view), None, 11, 0, 1.0, fake, fake, None, 0, 0, None,
+                             ctypes.byref(need), None) == B.SFC_EINVAL  # nq != n for cloud queries
+    assert lib.radius_search(ctypes.byref(view), None, 10, 0, float("nan"), fake, fake, None, 0, 0, None,
+                             ctypes.byref(need), None) == B.SFC_EINVAL
+    assert lib.radius_search(ctypes.byref(view), None, 10, 0, 1.0, fake, fake, None, 0, 0, None,
+                             ctypes.byref(need), None) == B.SFC_OK and need.value > 0
+    assert lib.knn_search(ctypes.byref(view), None, 10, 33, fake, fake, None, ctypes.byref(need), None) \
+        == B.SFC_ENOTSUP
+    assert lib.knn_search(ctypes.byref(view), None, 10, 0, fake, fake, None, ctypes.byref(need), None) \
+        == B.SFC_EINVAL
