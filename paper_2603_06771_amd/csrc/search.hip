@@ -631,9 +631,22 @@ __device__ __forceinline__ int64_t lower_bound_keys(const T *a, int64_t n, T v) 
 
 }  // namespace
 
+// k-NN in at most two exact rounds per wave.
+//  * tau_l (per lane) bounds the k-th distance from above: the largest d2 over
+//    the query's k curve neighbours.
+//  * Round 1 searches every active query out to R1 = the median of tau over
+//    the wave and inserts points with d2 <= R1.  A lane is done when tau_l <=
+//    R1 or its list is full with k-th d2 <= R1: every point that can still
+//    belong to its answer was within R1 and has been seen.
+//  * Round 2 serves the remaining lanes, each segment with its own radius (the
+//    largest tau of its lanes), inserting only points with d2 > R1 (those with
+//    d2 <= R1 were all seen in round 1), so no point is inserted twice.
+// Candidate nodes are pruned per lane only on near2 > bound (equality kept:
+// an equal d2 with a smaller index may still enter).
 template <int KMAX>
 __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
     __shared__ WaveLds L;
+    __shared__ float s_segr2[kSegMax];
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     const int lane = lane_id();
@@ -641,65 +654,127 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
     const Query q = load_query(a.queries, a.pts, row, a.nq);
     const int k = a.k;
 
-    // upper bound of the k-th distance: the farthest of the k curve neighbours
+    // tau: the largest d2 over a window of at least k consecutive curve
+    // points is an upper bound of the k-th distance; take the best of 5
+    // windows sliding over the 8 blocks of kb = ceil(k/4) points around the
+    // query's curve position (at a jump of the curve one window lies on the
+    // query's side)
     float tau = INFINITY;
     if (q.valid && a.n >= k) {
         int64_t pos = row;
         if (a.queries) pos = lower_bound_keys<uint64_t>(a.keys, a.n, point_key(q.x, q.y, q.z, *a.frame));
-        int64_t s = pos - k / 2;
-        if (s > a.n - k) s = a.n - k;
-        if (s < 0) s = 0;
-        tau = 0.0f;
-        for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(a.pts[s + i], q.x, q.y, q.z));
+        const int kb = (k + 3) / 4;
+        if (a.n >= 8 * kb) {
+            int64_t s0 = pos - 4 * kb;
+            if (s0 > a.n - 8 * kb) s0 = a.n - 8 * kb;
+            if (s0 < 0) s0 = 0;
+            float blk[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                float m = 0.0f;
+                for (int i = 0; i < kb; ++i) m = fmaxf(m, dist2(a.pts[s0 + b * kb + i], q.x, q.y, q.z));
+                blk[b] = m;
+            }
+#pragma unroll
+            for (int w = 0; w < 5; ++w)
+                tau = fminf(tau, fmaxf(fmaxf(blk[w], blk[w + 1]), fmaxf(blk[w + 2], blk[w + 3])));
+        } else {
+            int64_t s = pos - k / 2;
+            if (s > a.n - k) s = a.n - k;
+            if (s < 0) s = 0;
+            tau = 0.0f;
+            for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(a.pts[s + i], q.x, q.y, q.z));
+        }
     }
-    const float R2 = wave_max(q.valid ? tau : 0.0f);
-    const float R2open = R2 < INFINITY ? nextafterf(R2, INFINITY) : INFINITY;
-    const int nseg = make_segments(L, q, R2 < INFINITY ? 2.0f * sqrtf(R2) : INFINITY, nullptr);
+    // R1: median of tau over the valid lanes (bisection on the order-preserving
+    // bit pattern of non-negative floats)
+    const int nvalid = __popcll(ballot(q.valid));
+    const uint32_t tb = q.valid ? __float_as_uint(tau) : 0xFFFFFFFFu;
+    uint32_t lo = 0u, hi = 0x7F800000u;  // +inf
+    const int want = (nvalid + 1) / 2;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (__popcll(ballot(tb <= mid)) >= want)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const float R1 = __uint_as_float(lo);
 
     int64_t best[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) best[i] = i < k ? kPad : int64_t(-1);
 
-    auto accept = [&](const sfc_node &nd) { return segments_may_hit<SFC_SPHERE>(L, nseg, nd, 0.0f, R2open); };
-    auto sweep = [&](int ncand) {
-        for (int c0 = 0; c0 < ncand; c0 += kWave) {
-            const int m = min(kWave, ncand - c0);
-            float thr = tau;
-            const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
-            if (kth < thr) thr = kth;
-            uint64_t lm = 0;
-            if (q.valid) {
-                for (int i = 0; i < m; ++i) {
-                    const sfc_node nd = L.cand[c0 + i];
-                    float nx, fx, ny, fy, nz, fz;
-                    axis_range(nd.lo[0], nd.hi[0], q.x, nx, fx);
-                    axis_range(nd.lo[1], nd.hi[1], q.y, ny, fy);
-                    axis_range(nd.lo[2], nd.hi[2], q.z, nz, fz);
-                    const float near2 = fadd(fadd(fmul(nx, nx), fmul(ny, ny)), fmul(nz, nz));
-                    // equality kept: an equal d2 with a smaller index may still enter
-                    if (!(near2 > thr)) lm |= 1ull << i;
-                }
-            }
-            const uint64_t need = wave_or(lm);
-            if (!need) continue;
-            stage_rounds(L, a.pts, c0, m, need, [&](uint32_t n) {
-                for (uint32_t t = 0; t < n; ++t) {
-                    const float4 p = L.pts[t];
-                    const uint32_t o = L.owner[t];
-                    const float d = dist2(p, q.x, q.y, q.z);
-                    const int64_t x = pack(d, __float_as_uint(p.w));
-                    if (((lm >> o) & 1ull) && d <= tau && x < best[0]) {
-#pragma unroll
-                        for (int i = 0; i < KMAX; ++i) {
-                            const int64_t nxt = (i + 1 < KMAX) ? best[i + 1] : int64_t(-1);
-                            best[i] = nxt > x ? nxt : (best[i] > x ? x : best[i]);
-                        }
+    bool active = q.valid;
+    float lo2 = -1.0f;  // points with d2 <= lo2 were handled by an earlier round
+    for (int round = 0; round < 2; ++round) {
+        if (!ballot(active)) break;
+        const float bound = round == 0 ? fminf(R1, tau) : tau;  // per lane, inclusive
+        Query qa = q;
+        qa.valid = active;
+        const float bmax = wave_max_u(active ? bound : 0.0f);
+        const int nseg = make_segments(L, qa, bmax < INFINITY ? 2.0f * sqrtf(bmax) : INFINITY, nullptr);
+        // per-segment radius: the largest bound of its lanes (recomputed from
+        // the segment boxes written by make_segments)
+        for (int sg = 0; sg < nseg; ++sg) {
+            const bool in = active && q.x >= L.seg[sg][0] && q.x <= L.seg[sg][3] && q.y >= L.seg[sg][1] &&
+                            q.y <= L.seg[sg][4] && q.z >= L.seg[sg][2] && q.z <= L.seg[sg][5];
+            const float m = wave_max_u(in ? bound : 0.0f);
+            if (lane == 0) s_segr2[sg] = m < INFINITY ? nextafterf(m, INFINITY) : INFINITY;
+        }
+        __syncthreads();
+        auto accept = [&](const sfc_node &nd) {
+            bool hit = false;
+            for (int sg = 0; sg < nseg; ++sg)
+                hit = hit || group_may_hit<SFC_SPHERE>(nd, &L.seg[sg][0], &L.seg[sg][3], 0.0f, s_segr2[sg]);
+            return hit;
+        };
+        auto sweep = [&](int ncand) {
+            for (int c0 = 0; c0 < ncand; c0 += kWave) {
+                const int m = min(kWave, ncand - c0);
+                float thr = bound;
+                const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
+                if (kth < thr) thr = kth;
+                uint64_t lm = 0;
+                if (active) {
+                    for (int i = 0; i < m; ++i) {
+                        const sfc_node nd = L.cand[c0 + i];
+                        float nx, fx, ny, fy, nz, fz;
+                        axis_range(nd.lo[0], nd.hi[0], q.x, nx, fx);
+                        axis_range(nd.lo[1], nd.hi[1], q.y, ny, fy);
+                        axis_range(nd.lo[2], nd.hi[2], q.z, nz, fz);
+                        const float near2 = fadd(fadd(fmul(nx, nx), fmul(ny, ny)), fmul(nz, nz));
+                        const float far2 = fadd(fadd(fmul(fx, fx), fmul(fy, fy)), fmul(fz, fz));
+                        // equality kept: an equal d2 with a smaller index may still enter
+                        if (!(near2 > thr) && far2 > lo2) lm |= 1ull << i;
                     }
                 }
-            });
-        }
-    };
-    traverse(L, a.nodes, a.child, accept, sweep);
+                const uint64_t need = wave_or(lm);
+                if (!need) continue;
+                stage_rounds(L, a.pts, c0, m, need, [&](uint32_t n) {
+                    for (uint32_t t = 0; t < n; ++t) {
+                        const float4 p = L.pts[t];
+                        const uint32_t o = L.owner[t];
+                        const float d = dist2(p, q.x, q.y, q.z);
+                        const int64_t x = pack(d, __float_as_uint(p.w));
+                        if (((lm >> o) & 1ull) && d > lo2 && d <= bound && x < best[0]) {
+#pragma unroll
+                            for (int i = 0; i < KMAX; ++i) {
+                                const int64_t nxt = (i + 1 < KMAX) ? best[i + 1] : int64_t(-1);
+                                best[i] = nxt > x ? nxt : (best[i] > x ? x : best[i]);
+                            }
+                        }
+                    }
+                });
+            }
+        };
+        traverse(L, a.nodes, a.child, accept, sweep);
+        // done: the answer lies within the radius already searched
+        const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
+        if (round == 0) active = active && !(tau <= R1 || kth <= R1);
+        else active = false;
+        lo2 = R1;
+    }
     if (q.valid) {
         uint32_t *oi = a.idx + row * k;
         float *od = a.d2 + row * k;
