@@ -170,6 +170,61 @@ int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int 
 int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx,
                float *d2, void *ws, size_t *ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent clouds (no counterpart in the paper: the paper
+ * handles one cloud at a time; these run the same steps for many clouds in
+ * the same launches).  The input is the concatenation of the clouds' points;
+ * every kernel block works inside one cloud, so uneven sizes cost no padding.
+ * ---------------------------------------------------------------------- */
+
+/* One cloud of a batch: a HOST struct.  The library copies the table of B
+ * entries to the device on the caller's stream (pinned host memory makes the
+ * copy capturable in a graph). */
+typedef struct sfc_cloud {
+    int64_t offset;      /* first point of the cloud in the concatenated input */
+    int64_t n;           /* points of the cloud */
+    int32_t curve;       /* sfc_curve */
+    int32_t bits;        /* 1..21 */
+    uint32_t leaf_size;  /* N_max, >= 1 */
+    int32_t kernel;      /* radius search: sfc_kernel */
+    float r;             /* radius search: radius (r <= 0: empty rows) */
+    int32_t k;           /* k-NN: 1..32 */
+    int64_t q_offset;    /* search: first row of the cloud in the concatenated queries */
+    int64_t nq;          /* search: queries of the cloud (cloud queries: nq == n) */
+    sfc_octree tree;     /* filled by octree_batch_layout */
+} sfc_cloud;
+
+/* Lays out the trees of a batch in one block of tree memory: shared point /
+ * code / permutation arrays (cloud c at [offset_c, offset_c + n_c)), then the
+ * node arrays of every cloud (sized by the per-cloud bound of octree_bytes).
+ * Reads offset, n, bits, leaf_size of each cloud (offsets must be the running
+ * sum of the sizes); with tree_mem == NULL only *bytes is set, otherwise the
+ * `tree` views are filled with device pointers into tree_mem. */
+int octree_batch_layout(int B, sfc_cloud *clouds, void *tree_mem, size_t *bytes);
+
+/* Sections 4 and 5.1 for every cloud of the batch (encode with the cloud's
+ * own frame, stable sort by (cloud, code, index), reorder, build).  xyz holds
+ * the concatenated clouds; indices stored in the trees are local to each cloud.
+ * The trees must have been laid out by octree_batch_layout. */
+int build_linear_octree_batched(const float *xyz, int B, const sfc_cloud *clouds, void *ws, size_t *ws_bytes,
+                                void *stream);
+
+/* Radius search for every cloud of the batch with its own kernel and radius,
+ * in one launch per pass.  queries: concatenated per-cloud query blocks
+ * (cloud c at rows [q_offset_c, q_offset_c + nq_c)), or NULL (each cloud's own
+ * points, rows in the cloud's sorted order).  counts / offsets / indices form
+ * ONE CSR over all nq_total rows (offsets[nq_total] = total), indices local to
+ * each cloud.  Capacity and flags as for radius_search. */
+int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, uint32_t *counts,
+                          uint64_t *offsets, uint32_t *indices, uint64_t capacity, uint32_t flags, void *ws,
+                          size_t *ws_bytes, void *stream);
+
+/* k-NN for every cloud of the batch with its own k (<= kstride <= 32): row q
+ * occupies idx / d2 [q * kstride, (q + 1) * kstride); entries past the
+ * cloud's k are (0xFFFFFFFF, +inf). */
+int knn_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, int kstride,
+                       uint32_t *idx, float *d2, void *ws, size_t *ws_bytes, void *stream);
+
 /* Message of the last SFC_EINVAL / SFC_EHIP on the calling thread. */
 const char *sfc_last_error(void);
 

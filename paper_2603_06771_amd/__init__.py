@@ -14,7 +14,8 @@ from dataclasses import dataclass
 from . import _binding as B
 
 __all__ = ["encode_sfc", "build_linear_octree", "radius_search", "radius_count", "radius_fill", "knn_search", "Octree",
-           "CURVES", "KERNELS", "library_path"]
+           "Batch", "build_batch", "radius_search_batched", "knn_search_batched", "CURVES", "KERNELS",
+           "library_path"]
 
 CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
 KERNELS = {"sphere": B.SPHERE, "circle": B.CIRCLE, "cube": B.CUBE, "square": B.SQUARE}
@@ -243,4 +244,148 @@ def knn_search(tree: Octree, queries=None, k: int = 8):
     B.check(L.knn_search(*args, None, ctypes.byref(need), None), "knn_search(size)")
     ws = _ws(torch, need.value)
     B.check(L.knn_search(*args, _ptr(ws), ctypes.byref(need), _stream(torch)), "knn_search")
+    return idx, d2
+
+
+# ---------------------------------------------------------------- batches
+def _per_cloud(v, B_, name):
+    if isinstance(v, (list, tuple)):
+        if len(v) != B_:
+            raise ValueError(f"{name}: expected {B_} values, got {len(v)}")
+        return list(v)
+    return [v] * B_
+
+
+@dataclass
+class Batch:
+    """Trees of a batch of independent clouds built in one pass: `mem` owns
+    the device memory, `clouds` is the C table (sfc_cloud[B]) with each
+    cloud's tree view.  tree(c) gives an Octree view of cloud c that the
+    single-cloud calls accept."""
+    mem: object
+    clouds: object
+    sizes: list
+    offsets: list
+
+    @property
+    def B(self) -> int:
+        return len(self.sizes)
+
+    def tree(self, c: int) -> Octree:
+        t = self.clouds[c].tree
+        return Octree(mem=self.mem, view=t, curve=t.curve, bits=t.bits, leaf_size=t.leaf_size, n=t.n)
+
+
+def build_batch(xyz, sizes, curve="hilbert", bits=21, leaf_size=32) -> Batch:
+    """Sections 4 and 5.1 for a batch: xyz (n_total, 3) holds the clouds one
+    after the other (cloud c has sizes[c] points); curve, bits and leaf_size
+    are one value or one per cloud.  One launch sequence builds every tree."""
+    torch = _torch()
+    L = B.load()
+    xyz = _xyz(torch, xyz)
+    sizes = [int(x) for x in sizes]
+    nb = len(sizes)
+    if nb < 1 or sum(sizes) != xyz.shape[0]:
+        raise ValueError("sizes must be non-empty and sum to the number of points")
+    curves = _per_cloud(curve, nb, "curve")
+    bitss = _per_cloud(bits, nb, "bits")
+    leafs = _per_cloud(leaf_size, nb, "leaf_size")
+    clouds = (B.SfcCloud * nb)()
+    off = 0
+    offsets = []
+    for c in range(nb):
+        clouds[c].offset = off
+        clouds[c].n = sizes[c]
+        clouds[c].curve = _code(CURVES, curves[c])
+        clouds[c].bits = int(bitss[c])
+        clouds[c].leaf_size = int(leafs[c])
+        offsets.append(off)
+        off += sizes[c]
+    tb = ctypes.c_size_t(0)
+    B.check(L.octree_batch_layout(nb, clouds, None, ctypes.byref(tb)), "octree_batch_layout(size)")
+    mem = torch.empty(tb.value, dtype=torch.uint8, device="cuda")
+    B.check(L.octree_batch_layout(nb, clouds, _ptr(mem), ctypes.byref(tb)), "octree_batch_layout")
+    need = ctypes.c_size_t(0)
+    B.check(L.build_linear_octree_batched(_ptr(xyz), nb, clouds, None, ctypes.byref(need), None),
+            "build_linear_octree_batched(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.build_linear_octree_batched(_ptr(xyz), nb, clouds, _ptr(ws), ctypes.byref(need), _stream(torch)),
+            "build_linear_octree_batched")
+    return Batch(mem=mem, clouds=clouds, sizes=sizes, offsets=offsets)
+
+
+def _query_rows(torch, batch, queries, q_sizes):
+    """Sets q_offset / nq of every cloud; returns (queries, nq_total)."""
+    if queries is None:
+        for c in range(batch.B):
+            batch.clouds[c].q_offset = batch.offsets[c]
+            batch.clouds[c].nq = batch.sizes[c]
+        return None, sum(batch.sizes)
+    queries = _xyz(torch, queries)
+    q_sizes = [int(x) for x in q_sizes]
+    if len(q_sizes) != batch.B or sum(q_sizes) != queries.shape[0]:
+        raise ValueError("q_sizes must give one query count per cloud, summing to the number of queries")
+    off = 0
+    for c in range(batch.B):
+        batch.clouds[c].q_offset = off
+        batch.clouds[c].nq = q_sizes[c]
+        off += q_sizes[c]
+    return queries, off
+
+
+def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphere", r=1.0,
+                          capacity: int | None = None, prune: bool = True):
+    """Radius search of every cloud of the batch (its own kernel and radius)
+    in one launch per pass.  One CSR over all rows (cloud c's rows follow
+    cloud c - 1's); indices are local to each cloud.  queries=None: every
+    cloud's own points, rows in each cloud's sorted order."""
+    torch = _torch()
+    L = B.load()
+    kernels = _per_cloud(kernel, batch.B, "kernel")
+    radii = _per_cloud(r, batch.B, "r")
+    for c in range(batch.B):
+        batch.clouds[c].kernel = _code(KERNELS, kernels[c])
+        batch.clouds[c].r = float(radii[c])
+    queries, nq = _query_rows(torch, batch, queries, q_sizes)
+    flags = 0 if prune else B.NO_PRUNE
+    counts = torch.empty(nq, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    need = ctypes.c_size_t(0)
+    head = (batch.B, batch.clouds, _ptr(queries), nq, _ptr(counts), _ptr(offsets))
+    B.check(L.radius_search_batched(*head, None, 0, flags, None, ctypes.byref(need), None),
+            "radius_search_batched(size)")
+    ws = _ws(torch, need.value)
+    stream = _stream(torch)
+    if capacity is None:
+        B.check(L.radius_search_batched(*head, None, 0, flags, _ptr(ws), ctypes.byref(need), stream),
+                "radius_search_batched(count)")
+        total = int(offsets[nq].item())
+        indices = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        B.check(L.radius_search_batched(*head, _ptr(indices), total, flags | B.REUSE_COUNTS, _ptr(ws),
+                                        ctypes.byref(need), stream), "radius_search_batched(fill)")
+        return counts, offsets, indices[:total]
+    indices = torch.empty(max(int(capacity), 1), dtype=torch.int32, device="cuda")
+    B.check(L.radius_search_batched(*head, _ptr(indices), int(capacity), flags, _ptr(ws), ctypes.byref(need),
+                                    stream), "radius_search_batched")
+    return counts, offsets, indices
+
+
+def knn_search_batched(batch: Batch, queries=None, q_sizes=None, k=8, kstride: int | None = None):
+    """k-NN of every cloud of the batch (its own k) in one launch: (idx int32
+    [nq, kstride], d2 float32 [nq, kstride]); entries past a cloud's k are
+    (-1, +inf)."""
+    torch = _torch()
+    L = B.load()
+    ks = [int(x) for x in _per_cloud(k, batch.B, "k")]
+    kstride = int(kstride or max(ks))
+    for c in range(batch.B):
+        batch.clouds[c].k = ks[c]
+    queries, nq = _query_rows(torch, batch, queries, q_sizes)
+    idx = torch.empty((nq, kstride), dtype=torch.int32, device="cuda")
+    d2 = torch.empty((nq, kstride), dtype=torch.float32, device="cuda")
+    need = ctypes.c_size_t(0)
+    head = (batch.B, batch.clouds, _ptr(queries), nq, kstride, _ptr(idx), _ptr(d2))
+    B.check(L.knn_search_batched(*head, None, ctypes.byref(need), None), "knn_search_batched(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.knn_search_batched(*head, _ptr(ws), ctypes.byref(need), _stream(torch)), "knn_search_batched")
     return idx, d2

@@ -20,6 +20,7 @@ REUSE_COUNTS, NO_PRUNE = 1, 2
 
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
+           "octree_batch_layout", "build_linear_octree_batched", "radius_search_batched", "knn_search_batched",
            "sfc_last_error", "sfc_version")
 
 P = ctypes.c_void_p
@@ -49,6 +50,13 @@ class SfcOctree(ctypes.Structure):
     ]
 
 
+class SfcCloud(ctypes.Structure):
+    _fields_ = [
+        ("offset", I64), ("n", I64), ("curve", I32), ("bits", I32), ("leaf_size", U32), ("kernel", I32),
+        ("r", F32), ("k", I32), ("q_offset", I64), ("nq", I64), ("tree", SfcOctree),
+    ]
+
+
 class SfcError(RuntimeError):
     pass
 
@@ -71,9 +79,14 @@ def load(path: str = LIB_PATH):
     L.radius_search.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, F32, P, P, P, U64, U32, P,
                                 ctypes.POINTER(SZ), P]
     L.knn_search.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, P, P, P, ctypes.POINTER(SZ), P]
+    CL = ctypes.POINTER(SfcCloud)
+    L.octree_batch_layout.argtypes = [I32, CL, P, ctypes.POINTER(SZ)]
+    L.build_linear_octree_batched.argtypes = [P, I32, CL, P, ctypes.POINTER(SZ), P]
+    L.radius_search_batched.argtypes = [I32, CL, P, I64, P, P, P, U64, U32, P, ctypes.POINTER(SZ), P]
+    L.knn_search_batched.argtypes = [I32, CL, P, I64, I32, P, P, P, ctypes.POINTER(SZ), P]
     L.sfc_last_error.restype = ctypes.c_char_p
     L.sfc_version.restype = ctypes.c_char_p
-    for name in ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search"):
+    for name in EXPORTS[:-2]:
         getattr(L, name).restype = I32
     _lib = L
     return L

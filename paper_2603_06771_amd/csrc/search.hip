@@ -28,7 +28,10 @@
 //    of the k-th distance taken from the query's k curve neighbours.
 // Roofline: the fill pass is bound by HBM writes of the indices for large
 // neighbourhoods and by VALU (candidate tests) for small ones.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "codes.hpp"
 #include "internal.hpp"
@@ -326,20 +329,56 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
     }
 }
 
-struct RadiusArgs {
+// One cloud of a search launch (a table of these, or one in the kernel
+// arguments).  Rows of the cloud are global rows q_offset .. q_offset + nq - 1;
+// its groups of 64 rows are global groups g0 .. g0 + ceil(nq / 64) - 1.
+struct SearchCloud {
     const sfc_node *nodes;
     const int32_t *child;
     const float4 *pts;
-    const float *queries;
+    const uint64_t *keys;
+    const sfc_frame *frame;
+    int64_t n;
+    int64_t q_offset;
     int64_t nq;
-    int64_t groups;
+    int64_t g0;
     float r;
+    int32_t kernel;
+    int32_t k;
+    int32_t pad;
+};
+
+struct SearchArgs {
+    SearchCloud one;          // the cloud when tab is null
+    const SearchCloud *tab;   // [B] in device memory
+    int B;
+    int64_t groups;           // groups of all clouds
+    const float *queries;     // global rows (3 floats each), or null: each cloud's own sorted points
+    int64_t nq_total;
     uint32_t flags;
     uint32_t *counts;
     const uint64_t *offsets;
     uint32_t *indices;
     uint64_t capacity;
+    int kstride;
+    uint32_t *idx;
+    float *d2;
 };
+
+// the cloud owning global group g: the last table entry with g0 <= g (clouds
+// without rows own no group, so the search skips them)
+__device__ __forceinline__ SearchCloud group_cloud(const SearchArgs &a, int64_t g) {
+    if (!a.tab) return a.one;
+    int lo = 0, hi = a.B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tab[mid].g0 <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return a.tab[lo];
+}
 
 // Radius search.  Every candidate node is classified against the box of
 // every query segment (exactly, by the monotonicity argument): disjoint from
@@ -449,61 +488,57 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
     }
 }
 
-}  // namespace
-
 template <int KERNEL>
-__global__ __launch_bounds__(64) void k_radius_count(RadiusArgs a) {
-    __shared__ RadLds L;
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
+__device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
-    const int64_t row = g * kWave + lane;
-    const Query q = load_query(a.queries, a.pts, row, a.nq);
-    const float r = a.r, r2 = fmul(r, r);
+    const int64_t lr = lg * kWave + lane;  // row within the cloud
+    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
+    const float r = C.r, r2 = fmul(r, r);
     const bool prune = !(a.flags & SFC_NO_PRUNE);
-    int sid = 0;
-    const int nseg = make_segments(L, q, 2.0f * r, &sid);
     uint32_t cnt = 0;
-    auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
-    auto sweep = [&](int ncand) {
-        for (int c0 = 0; c0 < ncand; c0 += kWave) {
-            const int m = min(kWave, ncand - c0);
-            uint64_t mixed, touched, full;
-            const uint32_t len = classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
-            // contained for my segment and not swept: count the whole node
-            for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
-            if (!mixed) continue;
-            stage_union(L, a.pts, c0, m, mixed, len, [&](uint32_t n) {
-                uint32_t t = 0;
-                for (; t + 4 <= n; t += 4) {
-                    const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
-                    cnt += point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                    cnt += point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                    cnt += point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                    cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                }
-                for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
-            });
-        }
-    };
-    traverse(L, a.nodes, a.child, accept, sweep);
-    if (q.valid) a.counts[row] = cnt;
+    if (r > 0.0f) {
+        int sid = 0;
+        const int nseg = make_segments(L, q, 2.0f * r, &sid);
+        auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
+        auto sweep = [&](int ncand) {
+            for (int c0 = 0; c0 < ncand; c0 += kWave) {
+                const int m = min(kWave, ncand - c0);
+                uint64_t mixed, touched, full;
+                const uint32_t len =
+                    classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+                // contained for my segment and not swept: count the whole node
+                for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
+                if (!mixed) continue;
+                stage_union(L, C.pts, c0, m, mixed, len, [&](uint32_t n) {
+                    uint32_t t = 0;
+                    for (; t + 4 <= n; t += 4) {
+                        const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
+                        cnt += point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                        cnt += point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                        cnt += point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                        cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                    }
+                    for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                });
+            }
+        };
+        traverse(L, C.nodes, C.child, accept, sweep);
+    }
+    if (q.valid) a.counts[C.q_offset + lr] = cnt;
 }
 
 template <int KERNEL>
-__global__ __launch_bounds__(64) void k_radius_fill(RadiusArgs a) {
-    __shared__ FillLds L;
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
-    if (a.offsets[a.nq] > a.capacity) return;  // caller's buffer too small: write nothing
+__device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
-    const int64_t row = g * kWave + lane;
-    const Query q = load_query(a.queries, a.pts, row, a.nq);
-    const float r = a.r, r2 = fmul(r, r);
+    const int64_t lr = lg * kWave + lane;
+    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
+    const float r = C.r, r2 = fmul(r, r);
+    if (!(r > 0.0f)) return;  // empty rows
     const bool prune = !(a.flags & SFC_NO_PRUNE);
     int sid = 0;
     const int nseg = make_segments(L, q, 2.0f * r, &sid);
     // an invalid lane owns an empty row and never appends
+    const int64_t row = C.q_offset + lr;
     uint64_t gpos = q.valid ? a.offsets[row] : 0;
     const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;
     uint32_t nb = 0;
@@ -549,7 +584,7 @@ __global__ __launch_bounds__(64) void k_radius_fill(RadiusArgs a) {
             uint64_t mixed, touched, full;
             const uint32_t len = classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
             if (!touched) continue;
-            stage_union(L, a.pts, c0, m, touched, len, [&](uint32_t n) {
+            stage_union(L, C.pts, c0, m, touched, len, [&](uint32_t n) {
                 for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
                     flush(kRowCap - kChunk);
                     const uint32_t te = min(n, t0 + kChunk);
@@ -580,8 +615,41 @@ __global__ __launch_bounds__(64) void k_radius_fill(RadiusArgs a) {
             });
         }
     };
-    traverse(L, a.nodes, a.child, accept, sweep);
+    traverse(L, C.nodes, C.child, accept, sweep);
     flush(0);
+}
+
+}  // namespace
+
+// One wave per group of 64 queries of one cloud; the cloud's kernel selects
+// the (wave-uniform) body.
+__global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) {
+    __shared__ RadLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lg = g - C.g0;
+    switch (C.kernel) {
+    case SFC_SPHERE: radius_count_body<SFC_SPHERE>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE>(L, a, C, lg); break;
+    case SFC_CUBE: radius_count_body<SFC_CUBE>(L, a, C, lg); break;
+    default: radius_count_body<SFC_SQUARE>(L, a, C, lg); break;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
+    __shared__ FillLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lg = g - C.g0;
+    switch (C.kernel) {
+    case SFC_SPHERE: radius_fill_body<SFC_SPHERE>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_fill_body<SFC_CIRCLE>(L, a, C, lg); break;
+    case SFC_CUBE: radius_fill_body<SFC_CUBE>(L, a, C, lg); break;
+    default: radius_fill_body<SFC_SQUARE>(L, a, C, lg); break;
+    }
 }
 
 __global__ void k_zero_rows(uint32_t *counts, uint64_t *offsets, int64_t nq) {
@@ -594,21 +662,6 @@ __global__ void k_zero_rows(uint32_t *counts, uint64_t *offsets, int64_t nq) {
 
 // ------------------------------------------------------------------ k-NN
 namespace {
-
-struct KnnArgs {
-    const sfc_node *nodes;
-    const int32_t *child;
-    const float4 *pts;
-    const uint64_t *keys;
-    const sfc_frame *frame;
-    int64_t n;
-    const float *queries;
-    int64_t nq;
-    int64_t groups;
-    int k;
-    uint32_t *idx;
-    float *d2;
-};
 
 constexpr int64_t kPad = static_cast<int64_t>((0x7F800000ull << 32) | 0xFFFFFFFFull);  // (+inf, no index)
 
@@ -644,15 +697,17 @@ __device__ __forceinline__ int64_t lower_bound_keys(const T *a, int64_t n, T v) 
 // Candidate nodes are pruned per lane only on near2 > bound (equality kept:
 // an equal d2 with a smaller index may still enter).
 template <int KMAX>
-__global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
+__global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
     __shared__ WaveLds L;
     __shared__ float s_segr2[kSegMax];
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
     const int lane = lane_id();
-    const int64_t row = g * kWave + lane;
-    const Query q = load_query(a.queries, a.pts, row, a.nq);
-    const int k = a.k;
+    const int64_t lr = (g - C.g0) * kWave + lane;
+    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
+    const int k = C.k;
+    const int64_t n = C.n;
 
     // tau: the largest d2 over a window of at least k consecutive curve
     // points is an upper bound of the k-th distance; take the best of 5
@@ -660,19 +715,19 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
     // query's curve position (at a jump of the curve one window lies on the
     // query's side)
     float tau = INFINITY;
-    if (q.valid && a.n >= k) {
-        int64_t pos = row;
-        if (a.queries) pos = lower_bound_keys<uint64_t>(a.keys, a.n, point_key(q.x, q.y, q.z, *a.frame));
+    if (q.valid && n >= k) {
+        int64_t pos = lr;
+        if (a.queries) pos = lower_bound_keys<uint64_t>(C.keys, n, point_key(q.x, q.y, q.z, *C.frame));
         const int kb = (k + 3) / 4;
-        if (a.n >= 8 * kb) {
+        if (n >= 8 * kb) {
             int64_t s0 = pos - 4 * kb;
-            if (s0 > a.n - 8 * kb) s0 = a.n - 8 * kb;
+            if (s0 > n - 8 * kb) s0 = n - 8 * kb;
             if (s0 < 0) s0 = 0;
             float blk[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 float m = 0.0f;
-                for (int i = 0; i < kb; ++i) m = fmaxf(m, dist2(a.pts[s0 + b * kb + i], q.x, q.y, q.z));
+                for (int i = 0; i < kb; ++i) m = fmaxf(m, dist2(C.pts[s0 + b * kb + i], q.x, q.y, q.z));
                 blk[b] = m;
             }
 #pragma unroll
@@ -680,10 +735,10 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
                 tau = fminf(tau, fmaxf(fmaxf(blk[w], blk[w + 1]), fmaxf(blk[w + 2], blk[w + 3])));
         } else {
             int64_t s = pos - k / 2;
-            if (s > a.n - k) s = a.n - k;
+            if (s > n - k) s = n - k;
             if (s < 0) s = 0;
             tau = 0.0f;
-            for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(a.pts[s + i], q.x, q.y, q.z));
+            for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(C.pts[s + i], q.x, q.y, q.z));
         }
     }
     // R1: median of tau over the valid lanes (bisection on the order-preserving
@@ -751,8 +806,8 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
                 }
                 const uint64_t need = wave_or(lm);
                 if (!need) continue;
-                stage_rounds(L, a.pts, c0, m, need, [&](uint32_t n) {
-                    for (uint32_t t = 0; t < n; ++t) {
+                stage_rounds(L, C.pts, c0, m, need, [&](uint32_t cnt) {
+                    for (uint32_t t = 0; t < cnt; ++t) {
                         const float4 p = L.pts[t];
                         const uint32_t o = L.owner[t];
                         const float d = dist2(p, q.x, q.y, q.z);
@@ -768,7 +823,7 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
                 });
             }
         };
-        traverse(L, a.nodes, a.child, accept, sweep);
+        traverse(L, C.nodes, C.child, accept, sweep);
         // done: the answer lies within the radius already searched
         const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
         if (round == 0) active = active && !(tau <= R1 || kth <= R1);
@@ -776,8 +831,9 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
         lo2 = R1;
     }
     if (q.valid) {
-        uint32_t *oi = a.idx + row * k;
-        float *od = a.d2 + row * k;
+        const int64_t row = C.q_offset + lr;
+        uint32_t *oi = a.idx + row * a.kstride;
+        float *od = a.d2 + row * a.kstride;
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) {
             if (i < k) {
@@ -785,6 +841,10 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
                 oi[k - 1 - i] = static_cast<uint32_t>(v);
                 od[k - 1 - i] = __uint_as_float(static_cast<uint32_t>(v >> 32));
             }
+        }
+        for (int i = k; i < a.kstride; ++i) {
+            oi[i] = 0xFFFFFFFFu;
+            od[i] = INFINITY;
         }
     }
 }
@@ -794,9 +854,159 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
 // -------------------------------------------------------------- C ABI
 using namespace sfc;
 
-static bool tree_ok(const sfc_octree *t) {
+namespace {
+
+bool tree_ok(const sfc_octree *t) {
     return t && t->nodes && t->child && t->points && t->keys && t->frame && t->n >= 0;
 }
+
+SearchCloud cloud_entry(const sfc_octree &t, int64_t q_offset, int64_t nq, int64_t g0, int kernel, float r, int k) {
+    SearchCloud c;
+    c.nodes = t.nodes;
+    c.child = t.child;
+    c.pts = reinterpret_cast<const float4 *>(t.points);
+    c.keys = t.keys;
+    c.frame = t.frame;
+    c.n = t.n;
+    c.q_offset = q_offset;
+    c.nq = nq;
+    c.g0 = g0;
+    c.r = r;
+    c.kernel = kernel;
+    c.k = k;
+    c.pad = 0;
+    return c;
+}
+
+// Validates a batch for search and builds its host table; returns the total
+// group count, or -1 (error set) if the batch is malformed.
+int64_t search_table(const char *who, int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total,
+                     bool knn, int kstride, std::vector<SearchCloud> &tab) {
+    if (B < 1 || B > (1 << 20) || !clouds || nq_total < 0) {
+        set_error("%s: invalid batch", who);
+        return -1;
+    }
+    tab.resize(B);
+    int64_t rows = 0, g = 0;
+    for (int c = 0; c < B; ++c) {
+        const sfc_cloud &C = clouds[c];
+        const bool kernel_ok = knn ? (C.k >= 1 && C.k <= kstride) : (C.kernel >= 0 && C.kernel <= 3);
+        if (!tree_ok(&C.tree) || C.nq < 0 || C.q_offset != rows || !kernel_ok || std::isnan(C.r) ||
+            std::isinf(C.r) || (!queries && (C.nq != C.tree.n || C.q_offset != C.offset))) {
+            set_error("%s: cloud %d: invalid (rows must be consecutive; cloud queries need nq == n and "
+                      "q_offset == offset)", who, c);
+            return -1;
+        }
+        tab[c] = cloud_entry(C.tree, C.q_offset, C.nq, g, C.kernel, C.r, C.k);
+        rows += C.nq;
+        g += (C.nq + kWave - 1) / kWave;
+    }
+    if (rows != nq_total) {
+        set_error("%s: nq_total %lld differs from the sum of the clouds' nq (%lld)", who, (long long)nq_total,
+                  (long long)rows);
+        return -1;
+    }
+    return g;
+}
+
+// table entries per upload launch (kernel arguments stay under 4 KiB)
+constexpr int kTabChunk = 32;
+struct TabChunk {
+    SearchCloud c[kTabChunk];
+};
+
+}  // namespace
+
+__global__ void k_write_search_table(TabChunk chunk, int first, int count, SearchCloud *tab) {
+    const int i = threadIdx.x;
+    if (i < count) tab[first + i] = chunk.c[i];
+}
+
+namespace {
+
+int upload_table(const std::vector<SearchCloud> &tab, SearchCloud *dev, hipStream_t s) {
+    const int B = static_cast<int>(tab.size());
+    for (int first = 0; first < B; first += kTabChunk) {
+        TabChunk ch;
+        const int cnt = std::min(kTabChunk, B - first);
+        for (int i = 0; i < cnt; ++i) ch.c[i] = tab[first + i];
+        k_write_search_table<<<1, 64, 0, s>>>(ch, first, cnt, dev);
+        SFC_LAUNCH_CHECK("k_write_search_table");
+    }
+    return SFC_OK;
+}
+
+// workspace: [table][scan scratch]
+size_t search_ws_bytes(int B, int64_t nq_total, bool scan) {
+    Carver c(nullptr);
+    if (B > 1) c.take<SearchCloud>(B);
+    if (scan) c.take<char>(scan_ws_bytes(nq_total));
+    c.take<char>(256);
+    return c.bytes();
+}
+
+int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t groups, uint32_t *counts,
+                  void *ws, hipStream_t s) {
+    const int B = static_cast<int>(tab.size());
+    Carver cv(ws);
+    SearchCloud *dtab = B > 1 ? cv.take<SearchCloud>(B) : nullptr;
+    void *scan_ws = cv.take<char>(scan_ws_bytes(a.nq_total));
+    a.one = tab[0];
+    a.tab = dtab;
+    a.B = B;
+    a.groups = groups;
+    if (dtab) {
+        const int rc = upload_table(tab, dtab, s);
+        if (rc) return rc;
+    }
+    const unsigned grid = static_cast<unsigned>(xcd_grid(groups > 0 ? groups : 1));
+    if (!(a.flags & SFC_REUSE_COUNTS)) {
+        if (groups > 0) {
+            k_radius_count<<<grid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_count");
+        }
+        const int rc = scan_u32_to_u64(counts, a.nq_total, const_cast<uint64_t *>(a.offsets), true, scan_ws, s);
+        if (rc) return rc;
+    }
+    if (a.indices && groups > 0) {
+        k_radius_fill<<<grid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_radius_fill");
+    }
+    return SFC_OK;
+}
+
+int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t groups, int kmax, void *ws,
+               hipStream_t s) {
+    const int B = static_cast<int>(tab.size());
+    Carver cv(ws);
+    SearchCloud *dtab = B > 1 ? cv.take<SearchCloud>(B) : nullptr;
+    a.one = tab[0];
+    a.tab = dtab;
+    a.B = B;
+    a.groups = groups;
+    if (groups == 0) return SFC_OK;
+    if (dtab) {
+        const int rc = upload_table(tab, dtab, s);
+        if (rc) return rc;
+    }
+    const unsigned grid = static_cast<unsigned>(xcd_grid(groups));
+    if (kmax <= 8)
+        k_knn<8><<<grid, 64, 0, s>>>(a);
+    else if (kmax <= 16)
+        k_knn<16><<<grid, 64, 0, s>>>(a);
+    else
+        k_knn<32><<<grid, 64, 0, s>>>(a);
+    SFC_LAUNCH_CHECK("k_knn");
+    return SFC_OK;
+}
+
+SearchArgs blank_args() {
+    SearchArgs a;
+    memset(&a, 0, sizeof a);
+    return a;
+}
+
+}  // namespace
 
 extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
                              uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
@@ -806,7 +1016,7 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         set_error("radius_search: invalid argument");
         return SFC_EINVAL;
     }
-    const size_t need = scan_ws_bytes(nq);
+    const size_t need = search_ws_bytes(1, nq, true);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -823,41 +1033,46 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         }
         return SFC_OK;
     }
-    RadiusArgs a;
-    a.nodes = tree->nodes;
-    a.child = tree->child;
-    a.pts = reinterpret_cast<const float4 *>(tree->points);
+    std::vector<SearchCloud> tab(1, cloud_entry(*tree, 0, nq, 0, kernel, r, 0));
+    SearchArgs a = blank_args();
     a.queries = queries;
-    a.nq = nq;
-    a.groups = (nq + kWave - 1) / kWave;
-    a.r = r;
     a.flags = flags;
     a.counts = counts;
     a.offsets = offsets;
     a.indices = indices;
     a.capacity = capacity;
-    const unsigned grid = static_cast<unsigned>(xcd_grid(a.groups));
-    if (!(flags & SFC_REUSE_COUNTS)) {
-        switch (kernel) {
-        case SFC_SPHERE: k_radius_count<SFC_SPHERE><<<grid, 64, 0, s>>>(a); break;
-        case SFC_CIRCLE: k_radius_count<SFC_CIRCLE><<<grid, 64, 0, s>>>(a); break;
-        case SFC_CUBE: k_radius_count<SFC_CUBE><<<grid, 64, 0, s>>>(a); break;
-        default: k_radius_count<SFC_SQUARE><<<grid, 64, 0, s>>>(a); break;
-        }
-        SFC_LAUNCH_CHECK("k_radius_count");
-        const int rc = scan_u32_to_u64(counts, nq, offsets, true, ws, s);
-        if (rc) return rc;
+    a.nq_total = nq;
+    return radius_launch(a, tab, (nq + kWave - 1) / kWave, counts, ws, s);
+}
+
+extern "C" int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total,
+                                     uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
+                                     uint32_t flags, void *ws, size_t *ws_bytes, void *stream) {
+    if (!ws_bytes || !offsets || !counts) {
+        set_error("radius_search_batched: invalid argument");
+        return SFC_EINVAL;
     }
-    if (indices) {
-        switch (kernel) {
-        case SFC_SPHERE: k_radius_fill<SFC_SPHERE><<<grid, 64, 0, s>>>(a); break;
-        case SFC_CIRCLE: k_radius_fill<SFC_CIRCLE><<<grid, 64, 0, s>>>(a); break;
-        case SFC_CUBE: k_radius_fill<SFC_CUBE><<<grid, 64, 0, s>>>(a); break;
-        default: k_radius_fill<SFC_SQUARE><<<grid, 64, 0, s>>>(a); break;
-        }
-        SFC_LAUNCH_CHECK("k_radius_fill");
+    std::vector<SearchCloud> tab;
+    const int64_t groups = search_table("radius_search_batched", B, clouds, queries, nq_total, false, 0, tab);
+    if (groups < 0) return SFC_EINVAL;
+    const size_t need = search_ws_bytes(B, nq_total, true);
+    if (!ws) {
+        *ws_bytes = need;
+        return SFC_OK;
     }
-    return SFC_OK;
+    if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("radius_search_batched: workspace needs %zu bytes, 256-aligned", need);
+        return SFC_EWORKSPACE;
+    }
+    SearchArgs a = blank_args();
+    a.queries = queries;
+    a.flags = flags;
+    a.counts = counts;
+    a.offsets = offsets;
+    a.indices = indices;
+    a.capacity = capacity;
+    a.nq_total = nq_total;
+    return radius_launch(a, tab, groups, counts, ws, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx, float *d2,
@@ -870,7 +1085,7 @@ extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t 
         set_error("knn_search: k = %d above 32 is not supported", k);
         return SFC_ENOTSUP;
     }
-    const size_t need = 256;
+    const size_t need = search_ws_bytes(1, nq, false);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -879,28 +1094,45 @@ extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t 
         set_error("knn_search: workspace needs %zu bytes", need);
         return SFC_EWORKSPACE;
     }
-    if (nq == 0) return SFC_OK;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    KnnArgs a;
-    a.nodes = tree->nodes;
-    a.child = tree->child;
-    a.pts = reinterpret_cast<const float4 *>(tree->points);
-    a.keys = tree->keys;
-    a.frame = tree->frame;
-    a.n = tree->n;
+    std::vector<SearchCloud> tab(1, cloud_entry(*tree, 0, nq, 0, SFC_SPHERE, 0.0f, k));
+    SearchArgs a = blank_args();
     a.queries = queries;
-    a.nq = nq;
-    a.groups = (nq + kWave - 1) / kWave;
-    a.k = k;
+    a.nq_total = nq;
+    a.kstride = k;
     a.idx = idx;
     a.d2 = d2;
-    const unsigned grid = static_cast<unsigned>(xcd_grid(a.groups));
-    if (k <= 8)
-        k_knn<8><<<grid, 64, 0, s>>>(a);
-    else if (k <= 16)
-        k_knn<16><<<grid, 64, 0, s>>>(a);
-    else
-        k_knn<32><<<grid, 64, 0, s>>>(a);
-    SFC_LAUNCH_CHECK("k_knn");
-    return SFC_OK;
+    return knn_launch(a, tab, (nq + kWave - 1) / kWave, k, ws, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int knn_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, int kstride,
+                                  uint32_t *idx, float *d2, void *ws, size_t *ws_bytes, void *stream) {
+    if (!ws_bytes || kstride < 1 || (nq_total > 0 && (!idx || !d2))) {
+        set_error("knn_search_batched: invalid argument");
+        return SFC_EINVAL;
+    }
+    if (kstride > 32) {
+        set_error("knn_search_batched: kstride = %d above 32 is not supported", kstride);
+        return SFC_ENOTSUP;
+    }
+    std::vector<SearchCloud> tab;
+    const int64_t groups = search_table("knn_search_batched", B, clouds, queries, nq_total, true, kstride, tab);
+    if (groups < 0) return SFC_EINVAL;
+    const size_t need = search_ws_bytes(B, nq_total, false);
+    if (!ws) {
+        *ws_bytes = need;
+        return SFC_OK;
+    }
+    if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("knn_search_batched: workspace needs %zu bytes, 256-aligned", need);
+        return SFC_EWORKSPACE;
+    }
+    int kmax = 1;
+    for (int c = 0; c < B; ++c) kmax = std::max(kmax, clouds[c].k);
+    SearchArgs a = blank_args();
+    a.queries = queries;
+    a.nq_total = nq_total;
+    a.kstride = kstride;
+    a.idx = idx;
+    a.d2 = d2;
+    return knn_launch(a, tab, groups, kmax, ws, static_cast<hipStream_t>(stream));
 }

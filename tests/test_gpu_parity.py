@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2603_06771_amd import datagen
-from tests._parity import announce, assert_csr_equal
+from tests._parity import announce, assert_csr_equal, check_tree
 
 pytestmark = pytest.mark.gpu
 
@@ -67,29 +67,7 @@ def _check_tree(sfc, pts, curve, bits, leaf):
     import torch
     t = sfc.build_linear_octree(_dev(pts), curve, bits, leaf)
     torch.cuda.synchronize()
-    info = t.info()
-    rk, lo, s = oracle.encode(pts, curve, bits)
-    ks, perm = oracle.sort(rk)
-    ref = oracle.build_tree(pts, ks, perm, bits, leaf)
-    assert info["status"] == 0
-    assert np.array_equal(_u64(t.keys()), ks)
-    assert np.array_equal(t.perm().cpu().numpy().view(np.uint32), perm)
-    p = t.points().cpu().numpy()
-    assert np.array_equal(p[:, :3], pts[perm])
-    assert np.array_equal(p[:, 3].view(np.uint32), perm)
-    assert info["n_internal"] == ref["n_internal"] and info["n_leaves"] == ref["n_leaves"]
-    assert info["n_nodes"] == ref["n_nodes"]
-    arr = t.arrays(info)
-    assert np.array_equal(_u64(arr["leaves"]), ref["leaves"])
-    assert np.array_equal(arr["counts"].cpu().numpy().view(np.uint32), ref["counts"])
-    assert np.array_equal(arr["node_level"].cpu().numpy().astype(np.int32), ref["node_level"])
-    assert np.array_equal(_u64(arr["node_key"]), ref["node_start"])
-    nodes = arr["nodes"].cpu().numpy()
-    assert np.array_equal(nodes[:, 3].view(np.uint32).astype(np.int64), ref["node_begin"])
-    assert np.array_equal(nodes[:, 7].view(np.uint32).astype(np.int64), ref["node_end"])
-    assert np.array_equal(arr["child"].cpu().numpy().astype(np.int64), ref["node_child"])
-    box = np.concatenate([nodes[:, 0:3], nodes[:, 4:7]], axis=1)
-    assert np.array_equal(box, ref["node_box"])
+    check_tree(t, pts, curve, bits, leaf)
     return t
 
 
