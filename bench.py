@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
+    ap.add_argument("--workload", default="radius", choices=["radius", "batched"],
+                    help="radius: 10M LiDAR radius sweep (default); batched: 256 clouds, build + radius search")
+    ap.add_argument("--clouds", type=int, default=256, help="batched: number of clouds")
+    ap.add_argument("--tune-repeats", type=int, default=2, help="batched: timed steps per autotune candidate")
     return ap.parse_args()
 
 
@@ -81,12 +85,147 @@ def cpu_baseline(pts, sample: int):
                       f"{pts.shape[0]} queries: build {t_build:.2f} s, sample search {t_search:.2f} s"}
 
 
+def _events(torch, n):
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+
+def bench_batched(args):
+    """256 independent clouds (log-uniform 1e4..2e6 points, uniform / LiDAR,
+    per-cloud kernel and radius): build + radius search of every cloud.
+    Batched (one launch per stage for all clouds), eager and replayed from a
+    HIP graph, against one launch sequence per cloud (eager, and all of them
+    captured in one graph)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_06771_amd import autotune, datagen
+    from paper_2603_06771_amd.plan import BatchPlan
+
+    t0 = time.perf_counter()
+    clouds = datagen.batch_mix(args.clouds, seed=datagen.SEED_BATCH)
+    sizes = [c["points"].shape[0] for c in clouds]
+    kernels = [c["kernel"] for c in clouds]
+    radii = [c["radius"] for c in clouds]
+    xyz = torch.from_numpy(np.concatenate([c["points"] for c in clouds])).cuda()
+    n = int(sum(sizes))
+    del clouds
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    log(f"[bench] generated {len(sizes)} clouds, {n} points in {time.perf_counter() - t0:.1f} s")
+
+    tune = autotune.tune_leaf(xyz, sizes, kernels, radii, "hilbert", repeats=args.tune_repeats,
+                              cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"), log=log)
+    leaves = tune["leaf"]
+
+    plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii)
+    total = plan.total()
+    log(f"[bench] batched plan: {total} neighbours ({total * 4 / 1e9:.2f} GB)")
+
+    def timed(fn, steps):
+        ev = _events(torch, steps)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) * 1e3 / steps
+        return wall, float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    for _ in range(args.warmup):
+        plan.run()
+    eager_wall, eager_gpu = timed(plan.run, args.steps)
+    plan.capture()
+    for _ in range(args.warmup):
+        plan.replay()
+    graph_wall, graph_gpu = timed(plan.replay, args.steps)
+    batched_counts = plan.counts.clone()
+    log(f"[bench] batched eager {eager_wall:.2f} ms, graph {graph_wall:.2f} ms per step")
+
+    # kernel times inside the batched step (build, count, fill)
+    stage_ms = {}
+    ev = _events(torch, 3)
+    ev[0][0].record()
+    plan.build()
+    ev[0][1].record()
+    ev[1][0].record()
+    plan.search(count=True, fill=False)
+    ev[1][1].record()
+    ev[2][0].record()
+    plan.search(count=False, fill=True)
+    ev[2][1].record()
+    torch.cuda.synchronize()
+    for name, (a, b) in zip(("build", "count+scan", "fill"), ev):
+        stage_ms[name] = round(a.elapsed_time(b), 3)
+    del plan
+    torch.cuda.empty_cache()
+
+    # baseline: one launch sequence per cloud
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    singles = [BatchPlan(xyz[starts[c]:starts[c + 1]], [sizes[c]], "hilbert", 21, leaves[c], kernels[c], radii[c])
+               for c in range(len(sizes))]
+
+    def per_cloud():
+        for p in singles:
+            p.run()
+
+    for _ in range(args.warmup):
+        per_cloud()
+    base_wall, base_gpu = timed(per_cloud, args.steps)
+    same = all(torch.equal(p.counts, batched_counts[starts[c]:starts[c + 1]]) for c, p in enumerate(singles))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        per_cloud()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    base_graph_wall, base_graph_gpu = timed(g.replay, args.steps)
+    log(f"[bench] per-cloud eager {base_wall:.2f} ms, graph {base_graph_wall:.2f} ms per step; counts equal: {same}")
+
+    fill_bytes = 16 * n + 8 * (n + 1) + 4 * total
+    out = {
+        "metric": "batched build + radius-search queries/s (256 clouds, one HIP graph)",
+        "value": n / (graph_wall / 1e3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": graph_wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch256_mix_build_radius", "clouds": len(sizes), "points": n,
+                   "neighbours": total, "curve": "hilbert", "leaf": "autotuned per mu group"},
+        "batched": {"graph_ms": round(graph_wall, 3), "graph_gpu_ms": round(graph_gpu, 3),
+                    "eager_ms": round(eager_wall, 3), "eager_gpu_ms": round(eager_gpu, 3), "stages_ms": stage_ms},
+        "one_launch_sequence_per_cloud": {"eager_ms": round(base_wall, 3), "eager_gpu_ms": round(base_gpu, 3),
+                                          "graph_ms": round(base_graph_wall, 3),
+                                          "graph_gpu_ms": round(base_graph_gpu, 3), "counts_equal": same},
+        "speedup_vs_per_cloud": {"eager": base_wall / eager_wall, "graph": base_graph_wall / graph_wall,
+                                 "graph_vs_per_cloud_eager": base_wall / graph_wall},
+        "roofline": {"bound": "hbm", "kernel": "k_radius_fill", "achieved": fill_bytes / stage_ms["fill"] / 1e6,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_bytes / stage_ms["fill"] / 1e6 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "autotune": {"table_ms": tune["table"], "mu_edges": tune["edges"], "cached": tune["cached"],
+                     "leaf_histogram": {str(k): int(v) for k, v in zip(*np.unique(leaves, return_counts=True))}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split is "
               f"described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import numpy as np
     import torch
 
