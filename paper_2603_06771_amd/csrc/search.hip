@@ -21,8 +21,10 @@
 //    point's fp32 expression from the same side; the shortcuts therefore give
 //    bit-identical sets to testing every point.
 //  * Count pass writes per-query counts; fill pass writes the original
-//    indices: each lane appends to its own LDS row and full rows are flushed
-//    to HBM as one coalesced 64-lane store.
+//    indices: each lane appends the slots of its hits among the staged points
+//    to its own LDS row (one byte each), and rows are flushed to HBM with
+//    coalesced half-wave stores when they fill up and at the end of every
+//    staging round.
 //  * k-NN: lane-owned top-k of (d2, index) keys in registers (descending,
 //    so the current k-th is always register 0), seeded with an upper bound
 //    of the k-th distance taken from the query's k curve neighbours.
@@ -62,7 +64,8 @@ constexpr int kStage = SFC_STAGE;     // points staged per round
 constexpr int kRowCap = SFC_ROWCAP;   // fill: staged output entries per query
 constexpr int kChunk = SFC_CHUNK;     // fill: points swept between flush checks
 constexpr int kSegMax = 8;            // query segments per wave
-static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0, "tile parameters");
+static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0 && kStage <= 256,
+              "tile parameters");
 
 template <int KERNEL>
 __device__ __forceinline__ bool point_hit(const float4 &p, float qx, float qy, float qz, float r, float r2) {
@@ -397,8 +400,17 @@ struct RadLds {
     float seg[kSegMax][6];
 };
 
+// a row being flushed: global position, entries, entries that fit its slot
+struct RowFlush {
+    uint64_t pos;
+    uint32_t nb;
+    uint32_t lim;
+};
+
 struct FillLds : RadLds {
-    uint32_t rows[kWave * (kRowCap + 1)];  // per-query output staging
+    uint8_t rows[kWave * (kRowCap + 1)];   // per-query output staging: staged-point slots
+    RowFlush meta[kWave];
+    uint8_t flist[kWave];                  // lanes whose rows are flushed
 };
 
 // largest |fp32 difference| between a coordinate of [lo, hi] and one of [glo, ghi]
@@ -542,36 +554,32 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
     uint64_t gpos = q.valid ? a.offsets[row] : 0;
     const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;
     uint32_t nb = 0;
-    uint32_t *myrow = L.rows + lane * (kRowCap + 1);
+    uint8_t *myrow = L.rows + lane * (kRowCap + 1);
     uint32_t *out = a.indices;
     const int half = lane >> 5, hl = lane & 31;
 
     // Writes out every row holding more than `limit` entries, two rows per
     // step (one per half wave, 32 consecutive slots each: coalesced stores).
-    // Row cursors stay in their lanes' registers and are read with readlane.
+    // Each flushed row publishes its cursor in LDS (clamped to the row's end,
+    // so a row never spills into its neighbour) and joins a compact list.
     auto flush = [&](uint32_t limit) {
-        uint64_t fm = ballot(nb > limit);
+        const bool go = nb > limit;
+        const uint64_t fm = ballot(go);
         if (!fm) return;
-        __syncthreads();
-        while (fm) {
-            const int l0 = __ffsll(static_cast<long long>(fm)) - 1;
-            fm &= fm - 1;
-            int l1 = l0;
-            bool two = false;
-            if (fm) {
-                l1 = __ffsll(static_cast<long long>(fm)) - 1;
-                fm &= fm - 1;
-                two = true;
-            }
-            const uint32_t n0 = readlane_u32(nb, l0), n1 = two ? readlane_u32(nb, l1) : 0u;
-            const uint64_t b0 = readlane_u64(gpos, l0), b1 = readlane_u64(gpos, l1);
-            const uint64_t e0 = readlane_u64(gend, l0), e1 = readlane_u64(gend, l1);
-            const int l = half ? l1 : l0;
-            const uint32_t cl = half ? n1 : n0;
-            const uint64_t at = (half ? b1 : b0) + static_cast<uint64_t>(hl);
-            if (static_cast<uint32_t>(hl) < cl && at < (half ? e1 : e0)) out[at] = L.rows[l * (kRowCap + 1) + hl];
+        const int nf = __popcll(fm);
+        if (go) {
+            const uint64_t room = gend > gpos ? gend - gpos : 0ull;
+            L.meta[lane] = RowFlush{gpos, nb, static_cast<uint32_t>(room < nb ? room : nb)};
+            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
         }
-        if (nb > limit) {
+        __syncthreads();
+        for (int i = half; i < nf; i += 2) {
+            const int l = L.flist[i];
+            const RowFlush m = L.meta[l];
+            if (static_cast<uint32_t>(hl) < m.lim)
+                out[m.pos + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+        }
+        if (go) {
             gpos += nb;
             nb = 0;
         }
@@ -596,22 +604,23 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
                         const bool h2 = point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) & q.valid;
                         const bool h3 = point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) & q.valid;
                         // each slot is overwritten unless it holds a hit
-                        myrow[nb] = __float_as_uint(p0.w);
+                        myrow[nb] = static_cast<uint8_t>(t + 0);
                         nb += h0 ? 1u : 0u;
-                        myrow[nb] = __float_as_uint(p1.w);
+                        myrow[nb] = static_cast<uint8_t>(t + 1);
                         nb += h1 ? 1u : 0u;
-                        myrow[nb] = __float_as_uint(p2.w);
+                        myrow[nb] = static_cast<uint8_t>(t + 2);
                         nb += h2 ? 1u : 0u;
-                        myrow[nb] = __float_as_uint(p3.w);
+                        myrow[nb] = static_cast<uint8_t>(t + 3);
                         nb += h3 ? 1u : 0u;
                     }
                     for (; t < te; ++t) {
                         const float4 p = L.pts[t];
                         const bool h = point_hit<KERNEL>(p, q.x, q.y, q.z, r, r2) & q.valid;
-                        myrow[nb] = __float_as_uint(p.w);
+                        myrow[nb] = static_cast<uint8_t>(t);
                         nb += h ? 1u : 0u;
                     }
                 }
+                flush(0);  // the rows point into this round's staged points
             });
         }
     };
