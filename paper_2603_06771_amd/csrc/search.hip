@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "codes.hpp"
@@ -174,7 +175,10 @@ __device__ __forceinline__ Query load_query(const float *queries, const float4 *
 // Shared LDS of one wave: traversal stack, candidate nodes, staged points.
 struct WaveLds {
     int stack[kStack];
-    sfc_node cand[kCand];
+    int cand[kCand];         // candidate nodes (indices)
+    uint32_t cbeg[kCand];    // their point ranges
+    uint32_t cend[kCand];
+    sfc_node cnode[kCand];   // and the nodes themselves (per-lane pruning reads them in turn)
     float4 pts[kStage];
     uint8_t owner[kStage];   // candidate (within the batch) of each staged point
     uint32_t cincl[kWave];   // inclusive prefix of staged sizes of the batch
@@ -275,7 +279,13 @@ __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ no
         sp += 8 * allow;
         const bool cand = keep && !push;  // leaves, and internal nodes that found no stack room
         const uint64_t m_c = ballot(cand);
-        if (cand) L.cand[ncand + rank_below(m_c)] = nd;
+        if (cand) {
+            const int at = ncand + static_cast<int>(rank_below(m_c));
+            L.cand[at] = node;
+            L.cbeg[at] = nd.begin;
+            L.cend[at] = nd.end;
+            if constexpr (std::is_same<Lds, WaveLds>::value) L.cnode[at] = nd;
+        }
         ncand += __popcll(m_c);
         __syncthreads();
         if (ncand > kCand - kWave || (sp == 0 && ncand > 0)) {
@@ -305,7 +315,7 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
                                              Body body) {
     const int lane = lane_id();
     uint32_t sz = 0;
-    if (lane < m && ((need >> lane) & 1ull)) sz = L.cand[c0 + lane].end - L.cand[c0 + lane].begin;
+    if (lane < m && ((need >> lane) & 1ull)) sz = L.cend[c0 + lane] - L.cbeg[c0 + lane];
     const uint32_t incl = wave_inclusive_sum(sz);
     L.cincl[lane] = incl;
     const uint32_t total = __shfl(incl, kWave - 1);
@@ -323,7 +333,7 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
                     lo = mid + 1;
             }
             const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
-            L.pts[t] = pts[L.cand[c0 + lo].begin + (p - first)];
+            L.pts[t] = pts[L.cbeg[c0 + lo] + (p - first)];
             L.owner[t] = static_cast<uint8_t>(lo);
         }
         __syncthreads();
@@ -393,7 +403,9 @@ __device__ __forceinline__ SearchCloud group_cloud(const SearchArgs &a, int64_t 
 // segment and mixed for none are counted without touching their points.
 struct RadLds {
     int stack[kStack];
-    sfc_node cand[kCand];
+    int cand[kCand];         // candidate nodes (indices)
+    uint32_t cbeg[kCand];    // their point ranges
+    uint32_t cend[kCand];
     float4 pts[kStage];
     uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
     uint32_t clen[kWave];   // sizes of the batch candidates
@@ -444,12 +456,13 @@ __device__ __forceinline__ int classify_box(const sfc_node &b, const float *glo,
 // lane's own; *mixed / *touched: candidates mixed / not disjoint for some
 // segment; *full: candidates contained for the calling lane's segment.
 template <int KERNEL, typename Lds>
-__device__ __forceinline__ uint32_t classify_segments(Lds &L, int c0, int m, int nseg, int sid, float r, float r2,
-                                                      bool prune, uint64_t *mixed, uint64_t *touched, uint64_t *full) {
+__device__ __forceinline__ uint32_t classify_segments(Lds &L, const sfc_node *__restrict__ nodes, int c0, int m,
+                                                      int nseg, int sid, float r, float r2, bool prune,
+                                                      uint64_t *mixed, uint64_t *touched, uint64_t *full) {
     const int lane = lane_id();
     const bool have = lane < m;
     sfc_node nd;
-    if (have) nd = L.cand[c0 + lane];
+    if (have) nd = nodes[L.cand[c0 + lane]];
     const uint32_t len = have ? nd.end - nd.begin : 0u;
     L.clen[lane] = len;
     uint64_t mx = 0, tc = 0, fm = 0;
@@ -492,7 +505,7 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
                     lo = mid + 1;
             }
             const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
-            L.pts[t] = pts[L.cand[c0 + lo].begin + (p - first)];
+            L.pts[t] = pts[L.cbeg[c0 + lo] + (p - first)];
         }
         __syncthreads();
         body(cnt);
@@ -517,7 +530,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 const int m = min(kWave, ncand - c0);
                 uint64_t mixed, touched, full;
                 const uint32_t len =
-                    classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+                    classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
                 // contained for my segment and not swept: count the whole node
                 for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
                 if (!mixed) continue;
@@ -590,7 +603,7 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         for (int c0 = 0; c0 < ncand; c0 += kWave) {
             const int m = min(kWave, ncand - c0);
             uint64_t mixed, touched, full;
-            const uint32_t len = classify_segments<KERNEL>(L, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+            const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
             if (!touched) continue;
             stage_union(L, C.pts, c0, m, touched, len, [&](uint32_t n) {
                 for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
@@ -802,7 +815,7 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
                 uint64_t lm = 0;
                 if (active) {
                     for (int i = 0; i < m; ++i) {
-                        const sfc_node nd = L.cand[c0 + i];
+                        const sfc_node nd = L.cnode[c0 + i];
                         float nx, fx, ny, fy, nz, fz;
                         axis_range(nd.lo[0], nd.hi[0], q.x, nx, fx);
                         axis_range(nd.lo[1], nd.hi[1], q.y, ny, fy);
