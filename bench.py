@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
-    ap.add_argument("--workload", default="radius", choices=["radius", "batched"],
-                    help="radius: 10M LiDAR radius sweep (default); batched: 256 clouds, build + radius search")
+    ap.add_argument("--workload", default="radius", choices=["radius", "batched", "served"],
+                    help="radius: 10M LiDAR radius sweep (default); batched: 256 clouds, build + radius search; "
+                         "served: 64 resident clouds, Poisson radius / k-NN requests")
+    ap.add_argument("--requests", type=int, default=1500, help="served: requests per run")
+    ap.add_argument("--served-clouds", type=int, default=64, help="served: resident clouds")
     ap.add_argument("--clouds", type=int, default=256, help="batched: number of clouds")
     ap.add_argument("--tune-repeats", type=int, default=2, help="batched: timed steps per autotune candidate")
     return ap.parse_args()
@@ -217,6 +220,112 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _gen_served_cloud(args):
+    from paper_2603_06771_amd import datagen
+    n, seed = args
+    return datagen.lidar_tile(n, seed=seed)
+
+
+def bench_served(args):
+    """64 resident LiDAR clouds (3.5M..9M points each, Hilbert octrees in HBM);
+    a Poisson stream of requests, each naming a cloud, 1e3..1e6 of its points
+    as queries and a radius search (kernel, r ~ U(0.5, 3)) or a k-NN search
+    (k in 8, 16, 32).  Capacity is measured with every request queued at t=0;
+    then the stream is replayed at 50 / 80 / 95 % of the continuous-batching
+    capacity, by the continuous-batching server and by the one-request FIFO
+    server on the same GPU."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_2603_06771_amd import datagen, serve
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    sizes = datagen.served_sizes(args.served_clouds, seed=datagen.SEED_SERVED)
+    res = serve.Resident(budget_bytes=160 << 30, curve="hilbert", leaf_size=32)
+    t0 = time.perf_counter()
+    build_s = 0.0
+    group = 16
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        for g0 in range(0, len(sizes), group):
+            part = [(sizes[c], datagen.SEED_SERVED + 1 + c) for c in range(g0, min(len(sizes), g0 + group))]
+            clouds = pool.map(_gen_served_cloud, part)
+            torch.cuda.synchronize()
+            b0 = time.perf_counter()
+            ids = res.admit(clouds)
+            build_s += time.perf_counter() - b0
+            if ids is None:
+                raise SystemExit("served: clouds do not fit the memory budget")
+            del clouds
+    n_points = int(sum(sizes))
+    log(f"[bench] {len(sizes)} resident clouds, {n_points} points, {res.used / 1e9:.1f} GB; generated + built in "
+        f"{time.perf_counter() - t0:.1f} s (builds {build_s:.2f} s)")
+
+    base = datagen.request_stream(args.requests, len(sizes), sizes, rate_per_s=1.0)
+    log(f"[bench] {len(base)} requests, {sum(len(d['rows']) for d in base)} queries")
+
+    def requests(rate):
+        out = []
+        for d in base:
+            out.append(serve.Request(id=d["id"], arrival=0.0 if rate is None else d["arrival"] / rate,
+                                     cloud=d["cloud"], rows=d["rows"], op=d["op"], kernel=d.get("kernel", "sphere"),
+                                     radius=d.get("radius", 1.0), k=d.get("k", 8)))
+        return out
+
+    log("[bench] allocating server slots")
+    srv = serve.Server(res, slots=3, max_requests=64, max_queries=4 << 20, out_entries=1 << 30)
+    modes = {"continuous": dict(max_requests=64, n_slots=3), "fifo": dict(max_requests=1, n_slots=1)}
+
+    def summary(st):
+        lat = st["latency_s"] * 1e3
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "queries_per_s": st["queries"] / st["span_s"],
+                "requests_per_s": len(lat) / st["span_s"], "batches": st["batches"], "regrown": st["regrown"]}
+
+    log("[bench] server ready; warm-up")
+    srv.run(requests(None)[:64], log=log, **modes["continuous"])  # warm-up
+    cap = {}
+    for m, kw in modes.items():
+        log(f"[bench] capacity run, {m}")
+        st = srv.run(requests(None), log=log, **kw)
+        cap[m] = summary(st)
+        log(f"[bench] capacity {m}: {cap[m]['requests_per_s']:.0f} req/s, {cap[m]['queries_per_s']:.3g} q/s")
+    loads = {}
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * cap["continuous"]["requests_per_s"]
+        loads[str(frac)] = {}
+        for m, kw in modes.items():
+            st = srv.run(requests(rate), log=log, **kw)
+            loads[str(frac)][m] = summary(st)
+            log(f"[bench] load {frac:.2f} ({rate:.0f} req/s) {m}: p50 {loads[str(frac)][m]['p50_ms']:.2f} ms, "
+                f"p99 {loads[str(frac)][m]['p99_ms']:.2f} ms")
+    at95 = loads["0.95"]
+    out = {
+        "metric": "served p50/p99 latency at 95% of capacity (continuous batching), queries/s",
+        "value": at95["continuous"]["queries_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 64,
+        "ms_per_step": at95["continuous"]["mean_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served64_lidar_poisson", "clouds": len(sizes), "points": n_points,
+                   "requests": args.requests, "slots": 3, "max_batch_requests": 64},
+        "p50_ms": at95["continuous"]["p50_ms"],
+        "p99_ms": at95["continuous"]["p99_ms"],
+        "capacity": cap,
+        "loads": loads,
+        "resident_gb": res.used / 1e9,
+        "build_s": build_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -225,6 +334,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
         return
     import numpy as np
     import torch

@@ -152,9 +152,16 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
  *   flags     bit 0 (SFC_REUSE_COUNTS): counts/offsets already hold the
  *             result of a count call with identical arguments; skip it.
  *             bit 1 (SFC_NO_PRUNE): no containment shortcut (neighboursLin).
+ *             bit 2 (SFC_QUERIES_ORDERED): external queries are already in
+ *             a spatially coherent order (e.g. along the curve); skip the
+ *             internal reordering.  Without it, external queries are sorted
+ *             by their code in the tree's frame inside the call (workspace
+ *             grows by about 24 bytes per query); rows of the output always
+ *             follow the caller's query order.
  */
 #define SFC_REUSE_COUNTS 1u
 #define SFC_NO_PRUNE 2u
+#define SFC_QUERIES_ORDERED 4u
 int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
                   uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
                   uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
@@ -164,7 +171,9 @@ int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int 
  * the SPHERE expression above.  Ties in d2 are broken by the smaller index; a
  * query that is a cloud point finds itself at d2 = 0.  When k > n the missing
  * entries are (0xFFFFFFFF, +inf).
- *   queries  [3nq] fp32 (device) or NULL (every point, rows in sorted order)
+ *   queries  [3nq] fp32 (device) or NULL (every point, rows in sorted order);
+ *            external queries are reordered along the curve inside the call
+ *            (as radius_search without SFC_QUERIES_ORDERED)
  *   idx      [nq*k] output indices;  d2 [nq*k] output squared distances
  * 1 <= k <= 32 (SFC_ENOTSUP above). */
 int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx,
@@ -224,6 +233,13 @@ int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, 
  * cloud's k are (0xFFFFFFFF, +inf). */
 int knn_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, int kstride,
                        uint32_t *idx, float *d2, void *ws, size_t *ws_bytes, void *stream);
+
+/* Serving helper (not an operation of the paper): assembles a query batch
+ * from point ids.  out[3i .. 3i+2] = xyz[3 rows[i] .. 3 rows[i] + 2] for
+ * i < n, where xyz holds n_points points (AoS, 3 floats each); a row id
+ * >= n_points yields a NaN point (a query that matches nothing).  xyz, rows
+ * and out are device arrays; out must not overlap xyz.  No workspace. */
+int gather_points(const float *xyz, int64_t n_points, const uint32_t *rows, int64_t n, float *out, void *stream);
 
 /* Message of the last SFC_EINVAL / SFC_EHIP on the calling thread. */
 const char *sfc_last_error(void);

@@ -16,12 +16,12 @@ LIB_PATH = os.path.join(HERE, "libsfcoct.so")
 SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_ECAPACITY, SFC_EHIP, SFC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MORTON, HILBERT = 0, 1
 SPHERE, CIRCLE, CUBE, SQUARE = 0, 1, 2, 3
-REUSE_COUNTS, NO_PRUNE = 1, 2
+REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED = 1, 2, 4
 
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
            "octree_batch_layout", "build_linear_octree_batched", "radius_search_batched", "knn_search_batched",
-           "sfc_last_error", "sfc_version")
+           "gather_points", "sfc_last_error", "sfc_version")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.build_linear_octree_batched.argtypes = [P, I32, CL, P, ctypes.POINTER(SZ), P]
     L.radius_search_batched.argtypes = [I32, CL, P, I64, P, P, P, U64, U32, P, ctypes.POINTER(SZ), P]
     L.knn_search_batched.argtypes = [I32, CL, P, I64, I32, P, P, P, ctypes.POINTER(SZ), P]
+    L.gather_points.argtypes = [P, I64, P, I64, P, P]
     L.sfc_last_error.restype = ctypes.c_char_p
     L.sfc_version.restype = ctypes.c_char_p
     for name in EXPORTS[:-2]:

@@ -155,23 +155,6 @@ struct Query {
     bool valid;
 };
 
-__device__ __forceinline__ Query load_query(const float *queries, const float4 *pts, int64_t row, int64_t nq) {
-    Query q{0.0f, 0.0f, 0.0f, row < nq};
-    if (q.valid) {
-        if (queries) {
-            q.x = queries[3 * row];
-            q.y = queries[3 * row + 1];
-            q.z = queries[3 * row + 2];
-        } else {
-            const float4 p = pts[row];
-            q.x = p.x;
-            q.y = p.y;
-            q.z = p.z;
-        }
-    }
-    return q;
-}
-
 // Shared LDS of one wave: traversal stack, candidate nodes, staged points.
 struct WaveLds {
     int stack[kStack];
@@ -349,6 +332,7 @@ struct SearchCloud {
     const sfc_node *nodes;
     const int32_t *child;
     const float4 *pts;
+    const uint32_t *perm;
     const uint64_t *keys;
     const sfc_frame *frame;
     int64_t n;
@@ -367,6 +351,7 @@ struct SearchArgs {
     int B;
     int64_t groups;           // groups of all clouds
     const float *queries;     // global rows (3 floats each), or null: each cloud's own sorted points
+    const uint32_t *qperm;    // with queries: global row of every curve-sorted query position, or null
     int64_t nq_total;
     uint32_t flags;
     uint32_t *counts;
@@ -376,7 +361,32 @@ struct SearchArgs {
     int kstride;
     uint32_t *idx;
     float *d2;
+    uint32_t *spread;         // [groups] groups left to the one-query-per-wave kernels
+    uint32_t *nspread;        // their number
 };
+
+// Query of a lane (position lr in its cloud's rows) and the global row its
+// results go to.  External queries are taken in curve order through qperm,
+// so a wave's 64 queries are close in space whatever the caller's order.
+__device__ __forceinline__ Query lane_query(const SearchArgs &a, const SearchCloud &C, int64_t lr, int64_t *row) {
+    Query q{0.0f, 0.0f, 0.0f, lr < C.nq};
+    int64_t g = C.q_offset + lr;
+    if (q.valid) {
+        if (a.queries) {
+            if (a.qperm) g = a.qperm[g];
+            q.x = a.queries[3 * g];
+            q.y = a.queries[3 * g + 1];
+            q.z = a.queries[3 * g + 2];
+        } else {
+            const float4 p = C.pts[lr];
+            q.x = p.x;
+            q.y = p.y;
+            q.z = p.z;
+        }
+    }
+    *row = g;
+    return q;
+}
 
 // the cloud owning global group g: the last table entry with g0 <= g (clouds
 // without rows own no group, so the search skips them)
@@ -513,17 +523,97 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
     }
 }
 
+// A wave's queries are "spread" when the region every lane sweeps in the
+// group scheme (the segment boxes grown by r) is much larger than the
+// queries' own neighbourhoods together (nvalid cubes or squares of side 2r):
+// most of each lane's tests would then be other queries' work.  Such a wave
+// serves its queries one after another instead, all lanes on one query
+// (lane = candidate point).  Only the cost model uses these products, never
+// a result.
+// `factor` weighs the group scheme's per-point cost against the one-query
+// scheme's (k-NN group sweeps pay a register top-k insertion per point).
+template <typename Lds>
+__device__ __forceinline__ bool spread_group(const Lds &L, int nseg, float r, int nvalid, float factor = 1.0f) {
+    const float d = 2.0f * r;
+    float sweep = 0.0f;
+    for (int s = 0; s < nseg; ++s) sweep += (L.seg[s][3] - L.seg[s][0] + d) * (L.seg[s][4] - L.seg[s][1] + d);
+    return sweep > factor * static_cast<float>(nvalid) * d * d;
+}
+
+// Only external queries can be spread: a cloud's own points taken in curve
+// order are dense (64 consecutive curve points are close, apart from the few
+// jumps the segments already split off).
+__device__ __forceinline__ bool may_defer(const SearchArgs &a) { return a.spread && a.queries; }
+
+// hands group g to the one-query-per-wave kernel
+__device__ __forceinline__ void defer_group(const SearchArgs &a, int64_t g) {
+    if (lane_id() == 0) a.spread[atomicAdd(a.nspread, 1u)] = static_cast<uint32_t>(g);
+}
+
+// Walks the tree for the single query (qx, qy, qz); per batch of candidates
+// calls full(mask) with the candidates that are contained (all points are
+// neighbours) and sweep(n) for every staged round of the points of the mixed
+// ones.  Classification against the one-point box is the exact per-query
+// test (the box gap and far-corner distances equal those of the point).
+template <int KERNEL, typename Lds, typename Full, typename Sweep>
+__device__ __forceinline__ void walk_one(Lds &L, const SearchCloud &C, float qx, float qy, float qz, float r, float r2,
+                                         bool prune, Full full, Sweep sweep) {
+    if (lane_id() == 0) {
+        L.seg[0][0] = qx;
+        L.seg[0][1] = qy;
+        L.seg[0][2] = qz;
+        L.seg[0][3] = qx;
+        L.seg[0][4] = qy;
+        L.seg[0][5] = qz;
+    }
+    __syncthreads();
+    auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, 1, nd, r, r2); };
+    auto batches = [&](int ncand) {
+        for (int c0 = 0; c0 < ncand; c0 += kWave) {
+            const int m = min(kWave, ncand - c0);
+            uint64_t mixed, touched, fm;
+            const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, 1, 0, r, r2, prune, &mixed, &touched, &fm);
+            full(c0, fm & ~mixed, len);
+            if (mixed) stage_union(L, C.pts, c0, m, mixed, len, sweep);
+        }
+    };
+    traverse(L, C.nodes, C.child, accept, batches);
+}
+
+template <int KERNEL>
+__device__ __forceinline__ uint32_t count_one(RadLds &L, const SearchCloud &C, float qx, float qy, float qz, float r,
+                                              float r2, bool prune) {
+    const int lane = lane_id();
+    uint32_t cnt = 0;  // the same in every lane
+    walk_one<KERNEL>(
+        L, C, qx, qy, qz, r, r2, prune,
+        [&](int, uint64_t fm, uint32_t len) { cnt += wave_sum_u(((fm >> lane) & 1ull) ? len : 0u); },
+        [&](uint32_t n) {
+            for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
+                const uint32_t t = t0 + lane;
+                const bool h = t < n && point_hit<KERNEL>(L.pts[t < n ? t : 0], qx, qy, qz, r, r2);
+                cnt += static_cast<uint32_t>(__popcll(ballot(h)));
+            }
+        });
+    return cnt;
+}
+
 template <int KERNEL>
 __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
-    const int64_t lr = lg * kWave + lane;  // row within the cloud
-    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
+    const int64_t lr = lg * kWave + lane;  // position within the cloud's rows
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
     const float r = C.r, r2 = fmul(r, r);
     const bool prune = !(a.flags & SFC_NO_PRUNE);
     uint32_t cnt = 0;
+    int sid = 0;
+    const int nseg = r > 0.0f ? make_segments(L, q, 2.0f * r, &sid) : 0;
+    if (r > 0.0f && may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
+        defer_group(a, lg + C.g0);
+        return;
+    }
     if (r > 0.0f) {
-        int sid = 0;
-        const int nseg = make_segments(L, q, 2.0f * r, &sid);
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
             for (int c0 = 0; c0 < ncand; c0 += kWave) {
@@ -549,23 +639,60 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
         };
         traverse(L, C.nodes, C.child, accept, sweep);
     }
-    if (q.valid) a.counts[C.q_offset + lr] = cnt;
+    if (q.valid) a.counts[row] = cnt;
+}
+
+// One query's row [pos, end): contained candidates are copied from the
+// permutation (their points in sorted order), points of mixed ones are tested
+// with lane = point and compacted with ballot; both give coalesced stores.
+template <int KERNEL>
+__device__ __forceinline__ void fill_one(RadLds &L, const SearchCloud &C, float qx, float qy, float qz, float r,
+                                         float r2, bool prune, uint64_t pos, uint64_t end, uint32_t *out) {
+    const int lane = lane_id();
+    walk_one<KERNEL>(
+        L, C, qx, qy, qz, r, r2, prune,
+        [&](int c0, uint64_t fm, uint32_t) {
+            for (uint64_t b = fm; b; b &= b - 1) {
+                const int j = __ffsll(static_cast<long long>(b)) - 1;
+                const uint32_t beg = L.cbeg[c0 + j], len = L.clen[j];
+                for (uint32_t t0 = 0; t0 < len; t0 += kWave) {
+                    const uint32_t t = t0 + lane;
+                    if (t < len && pos + t < end) out[pos + t] = C.perm[beg + t];
+                }
+                pos += len;
+            }
+        },
+        [&](uint32_t n) {
+            for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
+                const uint32_t t = t0 + lane;
+                const float4 p = L.pts[t < n ? t : 0];
+                const bool h = t < n && point_hit<KERNEL>(p, qx, qy, qz, r, r2);
+                const uint64_t m = ballot(h);
+                const uint64_t at = pos + rank_below(m);
+                if (h && at < end) out[at] = __float_as_uint(p.w);
+                pos += static_cast<uint64_t>(__popcll(m));
+            }
+        });
 }
 
 template <int KERNEL>
 __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
-    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
     const float r = C.r, r2 = fmul(r, r);
     if (!(r > 0.0f)) return;  // empty rows
     const bool prune = !(a.flags & SFC_NO_PRUNE);
     int sid = 0;
     const int nseg = make_segments(L, q, 2.0f * r, &sid);
     // an invalid lane owns an empty row and never appends
-    const int64_t row = C.q_offset + lr;
     uint64_t gpos = q.valid ? a.offsets[row] : 0;
     const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;
+    if (may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
+        defer_group(a, lg + C.g0);
+        return;
+    }
     uint32_t nb = 0;
     uint8_t *myrow = L.rows + lane * (kRowCap + 1);
     uint32_t *out = a.indices;
@@ -674,6 +801,57 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
     }
 }
 
+// Deferred (spread) groups: one wave per query, grid-stride over the list.
+__global__ __launch_bounds__(64) void k_radius_count_spread(SearchArgs a) {
+    __shared__ RadLds L;
+    const int64_t total = static_cast<int64_t>(*a.nspread) * kWave;
+    for (int64_t j = xcd_item(blockIdx.x, gridDim.x); j < total; j += gridDim.x) {
+        const int64_t g = a.spread[j / kWave];
+        const SearchCloud C = group_cloud(a, g);
+        const int64_t lr = (g - C.g0) * kWave + (j % kWave);
+        if (lr >= C.nq) continue;
+        int64_t row;
+        const Query q = lane_query(a, C, lr, &row);
+        const float r = C.r, r2 = fmul(r, r);
+        const bool prune = !(a.flags & SFC_NO_PRUNE);
+        uint32_t c;
+        switch (C.kernel) {
+        case SFC_SPHERE: c = count_one<SFC_SPHERE>(L, C, q.x, q.y, q.z, r, r2, prune); break;
+        case SFC_CIRCLE: c = count_one<SFC_CIRCLE>(L, C, q.x, q.y, q.z, r, r2, prune); break;
+        case SFC_CUBE: c = count_one<SFC_CUBE>(L, C, q.x, q.y, q.z, r, r2, prune); break;
+        default: c = count_one<SFC_SQUARE>(L, C, q.x, q.y, q.z, r, r2, prune); break;
+        }
+        if (lane_id() == 0) a.counts[row] = c;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_radius_fill_spread(SearchArgs a) {
+    __shared__ RadLds L;
+    if (a.offsets[a.nq_total] > a.capacity) return;
+    const int64_t total = static_cast<int64_t>(*a.nspread) * kWave;
+    for (int64_t j = xcd_item(blockIdx.x, gridDim.x); j < total; j += gridDim.x) {
+        const int64_t g = a.spread[j / kWave];
+        const SearchCloud C = group_cloud(a, g);
+        const int64_t lr = (g - C.g0) * kWave + (j % kWave);
+        if (lr >= C.nq) continue;
+        int64_t row;
+        const Query q = lane_query(a, C, lr, &row);
+        const float r = C.r, r2 = fmul(r, r);
+        const bool prune = !(a.flags & SFC_NO_PRUNE);
+        const uint64_t pos = a.offsets[row], end = a.offsets[row + 1];
+        switch (C.kernel) {
+        case SFC_SPHERE: fill_one<SFC_SPHERE>(L, C, q.x, q.y, q.z, r, r2, prune, pos, end, a.indices); break;
+        case SFC_CIRCLE: fill_one<SFC_CIRCLE>(L, C, q.x, q.y, q.z, r, r2, prune, pos, end, a.indices); break;
+        case SFC_CUBE: fill_one<SFC_CUBE>(L, C, q.x, q.y, q.z, r, r2, prune, pos, end, a.indices); break;
+        default: fill_one<SFC_SQUARE>(L, C, q.x, q.y, q.z, r, r2, prune, pos, end, a.indices); break;
+        }
+    }
+}
+
+__global__ void k_reset_spread(uint32_t *nspread) {
+    if (threadIdx.x == 0) *nspread = 0;
+}
+
 __global__ void k_zero_rows(uint32_t *counts, uint64_t *offsets, int64_t nq) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= nq; i += stride) {
@@ -704,40 +882,16 @@ __device__ __forceinline__ int64_t lower_bound_keys(const T *a, int64_t n, T v) 
     return lo;
 }
 
-}  // namespace
-
-// k-NN in at most two exact rounds per wave.
-//  * tau_l (per lane) bounds the k-th distance from above: the largest d2 over
-//    the query's k curve neighbours.
-//  * Round 1 searches every active query out to R1 = the median of tau over
-//    the wave and inserts points with d2 <= R1.  A lane is done when tau_l <=
-//    R1 or its list is full with k-th d2 <= R1: every point that can still
-//    belong to its answer was within R1 and has been seen.
-//  * Round 2 serves the remaining lanes, each segment with its own radius (the
-//    largest tau of its lanes), inserting only points with d2 > R1 (those with
-//    d2 <= R1 were all seen in round 1), so no point is inserted twice.
-// Candidate nodes are pruned per lane only on near2 > bound (equality kept:
-// an equal d2 with a smaller index may still enter).
-template <int KMAX>
-__global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
-    __shared__ WaveLds L;
-    __shared__ float s_segr2[kSegMax];
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
-    const SearchCloud C = group_cloud(a, g);
-    const int lane = lane_id();
-    const int64_t lr = (g - C.g0) * kWave + lane;
-    const Query q = load_query(a.queries ? a.queries + 3 * C.q_offset : nullptr, C.pts, lr, C.nq);
-    const int k = C.k;
+// tau: the largest d2 over a window of at least k consecutive curve points
+// is an upper bound of the k-th distance; take the best of 5 windows sliding
+// over the 8 blocks of kb = ceil(k/4) points around the query's curve
+// position (at a jump of the curve one window lies on the query's side).
+// lr is the query's position in the cloud for cloud queries.
+__device__ __forceinline__ float curve_tau(const SearchArgs &a, const SearchCloud &C, const Query &q, int64_t lr,
+                                           int k) {
     const int64_t n = C.n;
-
-    // tau: the largest d2 over a window of at least k consecutive curve
-    // points is an upper bound of the k-th distance; take the best of 5
-    // windows sliding over the 8 blocks of kb = ceil(k/4) points around the
-    // query's curve position (at a jump of the curve one window lies on the
-    // query's side)
     float tau = INFINITY;
-    if (q.valid && n >= k) {
+    if (n >= k) {
         int64_t pos = lr;
         if (a.queries) pos = lower_bound_keys<uint64_t>(C.keys, n, point_key(q.x, q.y, q.z, *C.frame));
         const int kb = (k + 3) / 4;
@@ -763,6 +917,37 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
             for (int i = 0; i < k; ++i) tau = fmaxf(tau, dist2(C.pts[s + i], q.x, q.y, q.z));
         }
     }
+    return tau;
+}
+
+}  // namespace
+
+// k-NN in at most two exact rounds per wave.
+//  * tau_l (per lane) bounds the k-th distance from above: the largest d2 over
+//    the query's k curve neighbours.
+//  * Round 1 searches every active query out to R1 = the median of tau over
+//    the wave and inserts points with d2 <= R1.  A lane is done when tau_l <=
+//    R1 or its list is full with k-th d2 <= R1: every point that can still
+//    belong to its answer was within R1 and has been seen.
+//  * Round 2 serves the remaining lanes, each segment with its own radius (the
+//    largest tau of its lanes), inserting only points with d2 > R1 (those with
+//    d2 <= R1 were all seen in round 1), so no point is inserted twice.
+// Candidate nodes are pruned per lane only on near2 > bound (equality kept:
+// an equal d2 with a smaller index may still enter).
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
+    __shared__ WaveLds L;
+    __shared__ float s_segr2[kSegMax];
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int lane = lane_id();
+    const int64_t lr = (g - C.g0) * kWave + lane;
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
+    const int k = C.k;
+
+    const float tau = q.valid ? curve_tau(a, C, q, lr, k) : INFINITY;
     // R1: median of tau over the valid lanes (bisection on the order-preserving
     // bit pattern of non-negative floats)
     const int nvalid = __popcll(ballot(q.valid));
@@ -777,6 +962,13 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
             lo = mid + 1;
     }
     const float R1 = __uint_as_float(lo);
+    if (may_defer(a) && R1 > 0.0f && R1 < INFINITY) {
+        const int nseg0 = make_segments(L, q, 2.0f * sqrtf(R1), nullptr);
+        if (spread_group(L, nseg0, sqrtf(R1), nvalid, 0.25f)) {
+            defer_group(a, g);
+            return;
+        }
+    }
 
     int64_t best[KMAX];
 #pragma unroll
@@ -853,7 +1045,6 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
         lo2 = R1;
     }
     if (q.valid) {
-        const int64_t row = C.q_offset + lr;
         uint32_t *oi = a.idx + row * a.kstride;
         float *od = a.d2 + row * a.kstride;
 #pragma unroll
@@ -869,6 +1060,152 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
             od[i] = INFINITY;
         }
     }
+}
+
+// ---------------------------------------------------- k-NN of spread groups
+namespace {
+
+constexpr int kKnnBuf = 256;  // candidate keys held per query before a reduction
+
+struct KnnOneLds : RadLds {
+    int64_t buf[kKnnBuf];
+};
+
+// Keeps the k smallest of the cnt keys in L.buf (keys are distinct: the
+// index is part of them); returns the k-th smallest.  The k-th key is found
+// by bisection on the key value (counting keys <= mid over the wave).
+__device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds &L, int &cnt, int k) {
+    const int lane = lane_id();
+    int64_t v[kKnnBuf / kWave];
+#pragma unroll
+    for (int i = 0; i < kKnnBuf / kWave; ++i) {
+        const int e = lane + i * kWave;
+        v[i] = e < cnt ? L.buf[e] : INT64_MAX;
+    }
+    int64_t lo = 0, hi = INT64_MAX;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kKnnBuf / kWave; ++i) c += v[i] <= mid ? 1u : 0u;
+        if (static_cast<int>(wave_sum_u(c)) >= k)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    __syncthreads();
+    int at = 0;
+#pragma unroll
+    for (int i = 0; i < kKnnBuf / kWave; ++i) {
+        const bool keep = v[i] <= lo;
+        const uint64_t m = ballot(keep);
+        if (keep) L.buf[at + static_cast<int>(rank_below(m))] = v[i];
+        at += __popcll(m);
+    }
+    __syncthreads();
+    cnt = at;
+    return lo;
+}
+
+// k-NN of one query with the whole wave (lane = candidate point): every
+// point with d2 <= tau is a candidate (tau bounds the k-th distance), the
+// buffer is cut back to the k best when it fills, and the final k are ranked
+// by comparing every pair.
+__device__ __forceinline__ void knn_one(KnnOneLds &L, const SearchCloud &C, const Query &q, int k, float tau,
+                                        uint32_t *oi, float *od, int kstride) {
+    const int lane = lane_id();
+    int cnt = 0;
+    float bound = tau;  // inclusive
+    const float r2 = tau < INFINITY ? nextafterf(tau, INFINITY) : INFINITY;
+    walk_one<SFC_SPHERE>(
+        L, C, q.x, q.y, q.z, tau < INFINITY ? sqrtf(r2) : INFINITY, r2, false, [](int, uint64_t, uint32_t) {},
+        [&](uint32_t n) {
+            for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
+                if (cnt + kWave > kKnnBuf) {
+                    const int64_t kth = keep_k_smallest(L, cnt, k);
+                    bound = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(kth) >> 32));
+                }
+                const uint32_t t = t0 + lane;
+                const float4 p = L.pts[t < n ? t : 0];
+                const float d = dist2(p, q.x, q.y, q.z);
+                const bool h = t < n && d <= bound;
+                const uint64_t m = ballot(h);
+                if (h) L.buf[cnt + static_cast<int>(rank_below(m))] = pack(d, __float_as_uint(p.w));
+                cnt += __popcll(m);
+            }
+            __syncthreads();
+        });
+    if (cnt > k) keep_k_smallest(L, cnt, k);
+    const int64_t mine = lane < cnt ? L.buf[lane] : INT64_MAX;
+    int rank = 0;
+    for (int j = 0; j < cnt; ++j) rank += readlane_u64(static_cast<uint64_t>(mine), j) < static_cast<uint64_t>(mine);
+    if (lane < cnt) {
+        oi[rank] = static_cast<uint32_t>(static_cast<uint64_t>(mine));
+        od[rank] = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(mine) >> 32));
+    }
+    for (int i = cnt + lane; i < kstride; i += kWave) {
+        oi[i] = 0xFFFFFFFFu;
+        od[i] = INFINITY;
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_knn_spread(SearchArgs a) {
+    __shared__ KnnOneLds L;
+    const int64_t total = static_cast<int64_t>(*a.nspread) * kWave;
+    for (int64_t j = xcd_item(blockIdx.x, gridDim.x); j < total; j += gridDim.x) {
+        const int64_t g = a.spread[j / kWave];
+        const SearchCloud C = group_cloud(a, g);
+        const int64_t lr = (g - C.g0) * kWave + (j % kWave);
+        if (lr >= C.nq) continue;
+        int64_t row;
+        const Query q = lane_query(a, C, lr, &row);
+        // tau: the k-th smallest d2 over the 64 curve points around the
+        // query (lane j takes one of them), a bound of the k-th distance
+        const int k = C.k;
+        float tau = INFINITY;
+        if (C.n >= k) {
+            const int64_t w = C.n < kWave ? C.n : kWave;
+            int64_t pos = lr;
+            if (a.queries) pos = lower_bound_keys<uint64_t>(C.keys, C.n, point_key(q.x, q.y, q.z, *C.frame));
+            int64_t s0 = pos - w / 2;
+            if (s0 > C.n - w) s0 = C.n - w;
+            if (s0 < 0) s0 = 0;
+            const int lane = lane_id();
+            const uint32_t db = lane < w ? __float_as_uint(dist2(C.pts[s0 + lane], q.x, q.y, q.z)) : 0xFFFFFFFFu;
+            uint32_t lo = 0u, hi = 0x7F800000u;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (__popcll(ballot(db <= mid)) >= k)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            tau = __uint_as_float(lo);
+        }
+        knn_one(L, C, q, k, tau, a.idx + row * a.kstride, a.d2 + row * a.kstride, a.kstride);
+    }
+}
+
+// External queries in curve order: the code of every query in its cloud's
+// frame (same grid of one wave per 64 rows as the searches) ...
+__global__ __launch_bounds__(64) void k_query_keys(SearchArgs a, uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ perm) {
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lr = (g - C.g0) * kWave + lane_id();
+    if (lr >= C.nq) return;
+    const int64_t row = C.q_offset + lr;
+    keys[row] = point_key(a.queries[3 * row], a.queries[3 * row + 1], a.queries[3 * row + 2], *C.frame);
+    perm[row] = static_cast<uint32_t>(row);
+}
+
+// ... and the first row of every cloud (segments of the sort)
+__global__ void k_entry_starts(SearchArgs a, int64_t *starts) {
+    for (int c = threadIdx.x; c <= a.B; c += blockDim.x) starts[c] = c < a.B ? a.tab[c].q_offset : a.nq_total;
 }
 
 }  // namespace sfc
@@ -887,6 +1224,7 @@ SearchCloud cloud_entry(const sfc_octree &t, int64_t q_offset, int64_t nq, int64
     c.nodes = t.nodes;
     c.child = t.child;
     c.pts = reinterpret_cast<const float4 *>(t.points);
+    c.perm = t.perm;
     c.keys = t.keys;
     c.frame = t.frame;
     c.n = t.n;
@@ -959,20 +1297,74 @@ int upload_table(const std::vector<SearchCloud> &tab, SearchCloud *dev, hipStrea
 }
 
 // workspace: [table][scan scratch]
-size_t search_ws_bytes(int B, int64_t nq_total, bool scan) {
-    Carver c(nullptr);
-    if (B > 1) c.take<SearchCloud>(B);
-    if (scan) c.take<char>(scan_ws_bytes(nq_total));
+// Workspace: [table][scan scratch][query order: keys, perm, their copies,
+// sort scratch, cloud starts].
+struct SearchWs {
+    SearchCloud *tab = nullptr;
+    void *scan = nullptr;
+    uint64_t *keys = nullptr, *keys_alt = nullptr;
+    uint32_t *perm = nullptr, *perm_alt = nullptr;
+    void *radix = nullptr;
+    int64_t *starts = nullptr;
+    uint32_t *spread = nullptr;
+    uint32_t *nspread = nullptr;
+};
+
+bool wants_order(const float *queries, int64_t nq_total, uint32_t flags) {
+    return queries && !(flags & SFC_QUERIES_ORDERED) && nq_total > kWave;
+}
+
+size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem, SearchWs *w) {
+    Carver c(mem);
+    SearchWs x;
+    if (B > 1) x.tab = c.take<SearchCloud>(B);
+    if (scan) x.scan = c.take<char>(scan_ws_bytes(nq_total));
+    // groups: at most one per 64 rows of each cloud, so <= nq / 64 + B
+    x.spread = c.take<uint32_t>(nq_total / kWave + B + 1);
+    x.nspread = c.take<uint32_t>(1);
+    if (order) {
+        x.keys = c.take<uint64_t>(nq_total);
+        x.keys_alt = c.take<uint64_t>(nq_total);
+        x.perm = c.take<uint32_t>(nq_total);
+        x.perm_alt = c.take<uint32_t>(nq_total);
+        x.radix = c.take<char>(radix_ws_bytes(nq_total));
+        x.starts = c.take<int64_t>(B + 1);
+    }
     c.take<char>(256);
+    if (w) *w = x;
     return c.bytes();
+}
+
+size_t search_ws_bytes(int B, int64_t nq_total, bool scan, bool order = false) {
+    return carve_search_ws(B, nq_total, scan, order, nullptr, nullptr);
+}
+
+// Sorts the external queries of every cloud by their code (stable, so equal
+// codes keep the caller's order) and points a.qperm at the result.
+int order_queries(SearchArgs &a, const SearchWs &w, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(xcd_grid(a.groups));
+    k_query_keys<<<grid, 64, 0, s>>>(a, w.keys, w.perm);
+    SFC_LAUNCH_CHECK("k_query_keys");
+    if (a.B > 1) {
+        k_entry_starts<<<1, 256, 0, s>>>(a, w.starts);
+        SFC_LAUNCH_CHECK("k_entry_starts");
+    }
+    bool in_alt = false;
+    const int rc = radix_sort_pairs(w.keys, w.perm, w.keys_alt, w.perm_alt, a.nq_total, nullptr, 63, w.radix, s,
+                                    &in_alt, a.B > 1 ? w.starts : nullptr, a.B);
+    if (rc) return rc;
+    a.qperm = in_alt ? w.perm_alt : w.perm;
+    return SFC_OK;
 }
 
 int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t groups, uint32_t *counts,
                   void *ws, hipStream_t s) {
     const int B = static_cast<int>(tab.size());
-    Carver cv(ws);
-    SearchCloud *dtab = B > 1 ? cv.take<SearchCloud>(B) : nullptr;
-    void *scan_ws = cv.take<char>(scan_ws_bytes(a.nq_total));
+    const bool order = wants_order(a.queries, a.nq_total, a.flags);
+    SearchWs w;
+    carve_search_ws(B, a.nq_total, true, order, ws, &w);
+    SearchCloud *dtab = w.tab;
+    void *scan_ws = w.scan;
     a.one = tab[0];
     a.tab = dtab;
     a.B = B;
@@ -981,18 +1373,34 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
         const int rc = upload_table(tab, dtab, s);
         if (rc) return rc;
     }
+    if (order && groups > 0) {
+        const int rc = order_queries(a, w, s);
+        if (rc) return rc;
+    }
     const unsigned grid = static_cast<unsigned>(xcd_grid(groups > 0 ? groups : 1));
+    // spread groups: up to 64 waves each, grid-stride over the deferred list
+    const unsigned sgrid = static_cast<unsigned>(xcd_grid(std::min<int64_t>(groups * kWave, 1 << 16)));
+    a.spread = w.spread;
+    a.nspread = w.nspread;
     if (!(a.flags & SFC_REUSE_COUNTS)) {
         if (groups > 0) {
+            k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
+            SFC_LAUNCH_CHECK("k_reset_spread");
             k_radius_count<<<grid, 64, 0, s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_count");
+            k_radius_count_spread<<<sgrid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_count_spread");
         }
         const int rc = scan_u32_to_u64(counts, a.nq_total, const_cast<uint64_t *>(a.offsets), true, scan_ws, s);
         if (rc) return rc;
     }
     if (a.indices && groups > 0) {
+        k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
+        SFC_LAUNCH_CHECK("k_reset_spread");
         k_radius_fill<<<grid, 64, 0, s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");
+        k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_radius_fill_spread");
     }
     return SFC_OK;
 }
@@ -1000,8 +1408,10 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
 int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t groups, int kmax, void *ws,
                hipStream_t s) {
     const int B = static_cast<int>(tab.size());
-    Carver cv(ws);
-    SearchCloud *dtab = B > 1 ? cv.take<SearchCloud>(B) : nullptr;
+    const bool order = wants_order(a.queries, a.nq_total, 0);
+    SearchWs w;
+    carve_search_ws(B, a.nq_total, false, order, ws, &w);
+    SearchCloud *dtab = w.tab;
     a.one = tab[0];
     a.tab = dtab;
     a.B = B;
@@ -1011,7 +1421,15 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
         const int rc = upload_table(tab, dtab, s);
         if (rc) return rc;
     }
+    if (order) {
+        const int rc = order_queries(a, w, s);
+        if (rc) return rc;
+    }
     const unsigned grid = static_cast<unsigned>(xcd_grid(groups));
+    a.spread = w.spread;
+    a.nspread = w.nspread;
+    k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
+    SFC_LAUNCH_CHECK("k_reset_spread");
     if (kmax <= 8)
         k_knn<8><<<grid, 64, 0, s>>>(a);
     else if (kmax <= 16)
@@ -1019,6 +1437,8 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
     else
         k_knn<32><<<grid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn");
+    k_knn_spread<<<static_cast<unsigned>(xcd_grid(std::min<int64_t>(groups * kWave, 1 << 16))), 64, 0, s>>>(a);
+    SFC_LAUNCH_CHECK("k_knn_spread");
     return SFC_OK;
 }
 
@@ -1038,7 +1458,7 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         set_error("radius_search: invalid argument");
         return SFC_EINVAL;
     }
-    const size_t need = search_ws_bytes(1, nq, true);
+    const size_t need = search_ws_bytes(1, nq, true, wants_order(queries, nq, flags));
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -1077,7 +1497,7 @@ extern "C" int radius_search_batched(int B, const sfc_cloud *clouds, const float
     std::vector<SearchCloud> tab;
     const int64_t groups = search_table("radius_search_batched", B, clouds, queries, nq_total, false, 0, tab);
     if (groups < 0) return SFC_EINVAL;
-    const size_t need = search_ws_bytes(B, nq_total, true);
+    const size_t need = search_ws_bytes(B, nq_total, true, wants_order(queries, nq_total, flags));
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -1107,7 +1527,7 @@ extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t 
         set_error("knn_search: k = %d above 32 is not supported", k);
         return SFC_ENOTSUP;
     }
-    const size_t need = search_ws_bytes(1, nq, false);
+    const size_t need = search_ws_bytes(1, nq, false, wants_order(queries, nq, 0));
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -1139,7 +1559,7 @@ extern "C" int knn_search_batched(int B, const sfc_cloud *clouds, const float *q
     std::vector<SearchCloud> tab;
     const int64_t groups = search_table("knn_search_batched", B, clouds, queries, nq_total, true, kstride, tab);
     if (groups < 0) return SFC_EINVAL;
-    const size_t need = search_ws_bytes(B, nq_total, false);
+    const size_t need = search_ws_bytes(B, nq_total, false, wants_order(queries, nq_total, 0));
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;

@@ -124,27 +124,46 @@ def batch_mix(n_clouds: int = 256, seed: int = SEED_BATCH, n_min: float = 1e4, n
     return out
 
 
+def served_sizes(n_clouds: int = 64, seed: int = SEED_SERVED, n_min: float = 3.5e6, n_max: float = 9e6):
+    """Point counts of the resident clouds of the served workload (uniform in
+    [n_min, n_max]); cloud i is lidar_tile(sizes[i], seed + 1 + i)."""
+    rng = _rng(seed)
+    return [int(x) for x in np.round(rng.uniform(n_min, n_max, int(n_clouds)))]
+
+
+def _sample_rows(rng: np.random.Generator, n: int, k: int) -> np.ndarray:
+    """k distinct row ids of [0, n), ascending (draws with replacement, keeps
+    the distinct ones and tops up, then keeps a random subset of exactly k)."""
+    if 2 * k >= n:
+        return np.sort(rng.permutation(n)[:k]).astype(np.int64)
+    got = np.unique(rng.integers(0, n, k + k // 2 + 16))
+    while got.size < k:
+        got = np.unique(np.concatenate([got, rng.integers(0, n, k - got.size + 16)]))
+    return np.sort(rng.permutation(got)[:k]).astype(np.int64)
+
+
 def request_stream(n_requests: int, n_clouds: int, cloud_sizes, rate_per_s: float,
                    seed: int = SEED_STREAM, q_min: float = 1e3, q_max: float = 1e6):
-    """Poisson request stream: arrival time, cloud id, query rows (sampled
-    without replacement from that cloud), and either a radius search
-    (r ~ U(0.5, 3), kernel uniform) or a k-NN search (k in {8, 16, 32})."""
+    """Poisson request stream: arrival time, cloud id, query rows (distinct
+    points of that cloud), and either a radius search (r ~ U(0.5, 3), kernel
+    uniform) or a k-NN search (k in {8, 16, 32}).  Arrival times scale as
+    1 / rate_per_s; everything else does not depend on the rate."""
     rng = _rng(seed)
     kernels = ["sphere", "circle", "cube", "square"]
     t = 0.0
     out = []
     for i in range(int(n_requests)):
-        t += rng.exponential(1.0 / rate_per_s)
+        t += rng.exponential(1.0)
         cid = int(rng.integers(0, n_clouds))
         n = int(cloud_sizes[cid])
         nq = int(round(np.exp(rng.uniform(np.log(q_min), np.log(q_max)))))
         nq = max(1, min(nq, n))
-        rows = np.sort(rng.choice(n, nq, replace=False)).astype(np.int64)
+        rows = _sample_rows(rng, n, nq)
         if rng.random() < 0.5:
             req = {"op": "radius", "kernel": kernels[int(rng.integers(0, 4))],
                    "radius": float(np.float32(rng.uniform(0.5, 3.0)))}
         else:
             req = {"op": "knn", "k": int([8, 16, 32][int(rng.integers(0, 3))])}
-        req.update({"id": i, "arrival": t, "cloud": cid, "rows": rows})
+        req.update({"id": i, "arrival": t / float(rate_per_s), "cloud": cid, "rows": rows})
         out.append(req)
     return out

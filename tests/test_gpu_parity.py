@@ -146,6 +146,23 @@ def test_radius_external_queries(sfc):
         _radius_case(sfc, pts, "hilbert", 32, kernel, 2.0, queries=q)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_radius_sparse_queries(sfc, kernel):
+    # queries far apart (a small random subset of the cloud, and points off
+    # the cloud): waves take their queries one at a time
+    rng = np.random.default_rng(21)
+    pts = _cloud("lidar", 100000, seed=22)
+    sub = pts[np.sort(rng.choice(pts.shape[0], 700, replace=False))]
+    lo, hi = pts.min(0), pts.max(0)
+    off = (lo + (hi - lo) * rng.uniform(-0.05, 1.05, (300, 3))).astype(np.float32)
+    q = np.concatenate([sub, off]).astype(np.float32)
+    for r in (0.3, 1.5, 3.0):
+        announce(f"radius sparse queries {kernel} r={r}")
+        _radius_case(sfc, pts, "hilbert", 16, kernel, r, queries=q)
+        announce(f"radius sparse queries {kernel} r={r} no-prune")
+        _radius_case(sfc, pts, "morton", 32, kernel, r, queries=q, prune=False)
+
+
 def test_radius_no_prune_flag(sfc):
     pts = _cloud("lidar", 30000, seed=9)
     announce("radius no-prune")
@@ -206,6 +223,22 @@ def test_knn_lidar(sfc, k, curve):
     pts = _cloud("lidar", 40001, seed=12)
     announce(f"knn lidar k={k} {curve}")
     _knn_case(sfc, pts, curve, 32, k)
+
+
+@pytest.mark.parametrize("k", [1, 8, 32])
+def test_knn_sparse_queries(sfc, k):
+    # queries far apart: waves take them one at a time
+    rng = np.random.default_rng(23)
+    pts = _cloud("lidar", 100000, seed=24)
+    sub = pts[np.sort(rng.choice(pts.shape[0], 900, replace=False))]
+    lo, hi = pts.min(0), pts.max(0)
+    off = (lo + (hi - lo) * rng.uniform(-0.05, 1.05, (200, 3))).astype(np.float32)
+    q = np.concatenate([sub, off]).astype(np.float32)
+    announce(f"knn sparse queries k={k}")
+    _knn_case(sfc, pts, "hilbert", 16, k, queries=q)
+    announce(f"knn sparse queries k={k}, duplicates")
+    dup = _cloud("dup", 30000, seed=25)
+    _knn_case(sfc, dup, "morton", 8, k, queries=dup[np.sort(rng.choice(dup.shape[0], 500, replace=False))])
 
 
 def test_knn_duplicates_ties(sfc):
