@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
 
     python -m paper_2603_06771_amd.rocprof_summary stats <kernel_stats.csv>
+    python -m paper_2603_06771_amd.rocprof_summary trace <kernel_trace.csv> <kernel-name-prefix> [min_us]
     python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> [kernel-substring]
 
@@ -25,6 +26,27 @@ def stats(path: str, top: int = 25) -> str:
         out.append(f"{r['Name'][:70]:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                    f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
     return "\n".join(out)
+
+
+def trace(path: str, kernel: str, min_us: float = 100.0) -> str:
+    """Per-dispatch durations of the kernels whose name starts with `kernel`
+    (after any namespace), dispatches shorter than min_us left out (e.g.
+    fills launched with a zero capacity, which return at once)."""
+    durs, short = [], 0
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].split("(")[0].split("::")[-1]
+        if name != kernel:
+            continue
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        if us < min_us:
+            short += 1
+        else:
+            durs.append(us)
+    if not durs:
+        return f"{kernel}: no dispatch of at least {min_us} us ({short} shorter)"
+    return (f"{kernel}: {len(durs)} dispatches >= {min_us:g} us (+{short} shorter, left out): "
+            f"avg {statistics.mean(durs):.1f} us, median {statistics.median(durs):.1f} us, "
+            f"min {min(durs):.1f} us, max {max(durs):.1f} us")
 
 
 def _per_dispatch(path: str, counter: str):
@@ -91,6 +113,8 @@ def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, m
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+    elif sys.argv[1] == "trace":
+        print(trace(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else 100.0))
     elif sys.argv[1] == "record":
         import json
         print(json.dumps(traffic_record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5]), indent=1))
