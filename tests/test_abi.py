@@ -103,3 +103,42 @@ def test_search_argument_validation(lib):
         == B.SFC_ENOTSUP
     assert lib.knn_search(ctypes.byref(view), None, 10, 0, fake, fake, None, ctypes.byref(need), None) \
         == B.SFC_EINVAL
+
+
+def test_batched_host_validation(lib):
+    nb = 3
+    cl = (B.SfcCloud * nb)()
+    off = 0
+    for c, n in enumerate((1000, 0, 50)):
+        cl[c].offset, cl[c].n, cl[c].curve, cl[c].bits, cl[c].leaf_size = off, n, 1, 21, 16
+        off += n
+    need = ctypes.c_size_t(0)
+    assert lib.octree_batch_layout(nb, cl, None, ctypes.byref(need)) == B.SFC_OK and need.value > 0
+    # the layout size of a batch of one equals octree_bytes
+    one = (B.SfcCloud * 1)()
+    one[0].n, one[0].curve, one[0].bits, one[0].leaf_size = 1000, 1, 21, 16
+    b1, b2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.octree_batch_layout(1, one, None, ctypes.byref(b1)) == B.SFC_OK
+    assert lib.octree_bytes(1000, 16, 21, ctypes.byref(b2)) == B.SFC_OK and b1.value == b2.value
+    # offsets must be the running sum of the sizes
+    cl[2].offset = 999
+    assert lib.octree_batch_layout(nb, cl, None, ctypes.byref(need)) == B.SFC_EINVAL
+    cl[2].offset = 1000
+    cl[1].leaf_size = 0
+    assert lib.build_linear_octree_batched(None, nb, cl, None, ctypes.byref(need), None) == B.SFC_EINVAL
+    cl[1].leaf_size = 16
+    assert lib.build_linear_octree_batched(None, nb, cl, None, ctypes.byref(need), None) == B.SFC_OK
+    assert need.value > 0
+    # searches: trees not laid out -> rejected; kstride above 32 -> not supported
+    fake = ctypes.c_void_p(256)
+    assert lib.radius_search_batched(nb, cl, None, 1050, fake, fake, None, 0, 0, None, ctypes.byref(need),
+                                     None) == B.SFC_EINVAL
+    assert lib.knn_search_batched(nb, cl, None, 1050, 33, fake, fake, None, ctypes.byref(need), None) \
+        == B.SFC_ENOTSUP
+
+
+def test_gather_points_validation(lib):
+    fake = ctypes.c_void_p(256)
+    assert lib.gather_points(fake, 10, fake, 0, fake, None) == B.SFC_OK  # nothing to do, nothing launched
+    assert lib.gather_points(fake, 10, None, 5, fake, None) == B.SFC_EINVAL
+    assert lib.gather_points(fake, -1, fake, 5, fake, None) == B.SFC_EINVAL
