@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
 
     python -m paper_2603_06771_amd.rocprof_summary stats <kernel_stats.csv>
-    python -m paper_2603_06771_amd.rocprof_summary trace <kernel_trace.csv> <kernel-name-prefix> [min_us]
+    python -m paper_2603_06771_amd.rocprof_summary trace <kernel_trace.csv> <kernel-name> [min_us]
+    python -m paper_2603_06771_amd.rocprof_summary sq <counter_collection.csv> <kernel-name>
     python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> [kernel-substring]
 
@@ -47,6 +48,30 @@ def trace(path: str, kernel: str, min_us: float = 100.0) -> str:
     return (f"{kernel}: {len(durs)} dispatches >= {min_us:g} us (+{short} shorter, left out): "
             f"avg {statistics.mean(durs):.1f} us, median {statistics.median(durs):.1f} us, "
             f"min {min(durs):.1f} us, max {max(durs):.1f} us")
+
+
+def sq(path: str, kernel: str) -> str:
+    """Per-dispatch instruction mix of `kernel` from SQ counters: instructions,
+    wait and wave cycles per wave."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Kernel_Name"].split("(")[0].split("::")[-1] != kernel:
+            continue
+        d = per.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["dur_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    out = [f"{'dispatch':>8s} {'dur_us':>9s} {'waves':>8s} {'VALU/w':>8s} {'SALU/w':>8s} {'LDS/w':>7s} "
+           f"{'VMEM/w':>7s} {'wait/w':>8s} {'cycles/w':>9s}"]
+    for dsp in sorted(per):
+        d = per[dsp]
+        w = max(d.get("SQ_WAVES_sum", d.get("SQ_WAVES", 1.0)), 1.0)
+
+        def g(name):
+            return d.get(name + "_sum", d.get(name, float("nan")))
+        out.append(f"{dsp:8d} {d['dur_us']:9.0f} {w:8.0f} {g('SQ_INSTS_VALU') / w:8.0f} {g('SQ_INSTS_SALU') / w:8.0f} "
+                   f"{g('SQ_INSTS_LDS') / w:7.0f} {g('SQ_INSTS_VMEM_RD') / w:7.0f} {g('SQ_WAIT_INST_ANY') / w:8.0f} "
+                   f"{g('SQ_WAVE_CYCLES') / w:9.0f}")
+    return "\n".join(out)
 
 
 def _per_dispatch(path: str, counter: str):
@@ -113,6 +138,8 @@ def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, m
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+    elif sys.argv[1] == "sq":
+        print(sq(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "trace":
         print(trace(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else 100.0))
     elif sys.argv[1] == "record":
