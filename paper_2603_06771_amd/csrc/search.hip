@@ -65,7 +65,7 @@ constexpr int kStage = SFC_STAGE;     // points staged per round
 constexpr int kRowCap = SFC_ROWCAP;   // fill: staged output entries per query
 constexpr int kChunk = SFC_CHUNK;     // fill: points swept between flush checks
 constexpr int kSegMax = 8;            // query segments per wave
-static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0 && kStage <= 256,
+static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0 && kStage >= 64 && kStage <= 256,
               "tile parameters");
 
 template <int KERNEL>
@@ -492,20 +492,26 @@ __device__ __forceinline__ uint32_t classify_segments(Lds &L, const sfc_node *__
 }
 
 // Stages the points of the batch candidates [c0, c0 + m) selected by `need`
-// (bit i: candidate c0 + i), in candidate order, kStage points per round, and
-// calls body(count) with L.pts[0..count) filled.
-template <typename Lds, typename Body>
+// (bit i: candidate c0 + i), in candidate order, and calls body(count) with
+// L.pts[0..count) filled, up to kStage points per round.  Points that no
+// query of any segment can reach are dropped while staging (lane = point,
+// the conservative gap test of the segment boxes, exact by the monotonicity
+// argument): a point outside every grown segment box is a neighbour of none
+// of the wave's queries, so only the sweep's work changes, never a result.
+template <int KERNEL, typename Lds, typename Body>
 __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
-                                            uint32_t len, Body body) {
+                                            uint32_t len, int nseg, float r, float r2, Body body) {
     const int lane = lane_id();
     const uint32_t incl = wave_inclusive_sum(((need >> lane) & 1ull) ? len : 0u);
     L.cincl[lane] = incl;
     const uint32_t total = __shfl(incl, kWave - 1);
     __syncthreads();
-    for (uint32_t done = 0; done < total; done += kStage) {
-        const uint32_t cnt = min(static_cast<uint32_t>(kStage), total - done);
-        for (uint32_t t = lane; t < cnt; t += kWave) {
-            const uint32_t p = done + t;
+    uint32_t kept = 0;  // points staged for the next round (the same in every lane)
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t p = base + lane;
+        bool keep = false;
+        float4 v;
+        if (p < total) {
             int lo = 0, hi = m - 1;  // first candidate whose inclusive end exceeds p
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -515,11 +521,22 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
                     lo = mid + 1;
             }
             const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
-            L.pts[t] = pts[L.cbeg[c0 + lo] + (p - first)];
+            v = pts[L.cbeg[c0 + lo] + (p - first)];
+            sfc_node b;
+            b.lo[0] = b.hi[0] = v.x;
+            b.lo[1] = b.hi[1] = v.y;
+            b.lo[2] = b.hi[2] = v.z;
+            keep = segments_may_hit<KERNEL>(L, nseg, b, r, r2);
         }
-        __syncthreads();
-        body(cnt);
-        __syncthreads();
+        const uint64_t km = ballot(keep);
+        if (keep) L.pts[kept + rank_below(km)] = v;
+        kept += static_cast<uint32_t>(__popcll(km));
+        if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
+            __syncthreads();
+            body(kept);
+            __syncthreads();
+            kept = 0;
+        }
     }
 }
 
@@ -574,7 +591,7 @@ __device__ __forceinline__ void walk_one(Lds &L, const SearchCloud &C, float qx,
             uint64_t mixed, touched, fm;
             const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, 1, 0, r, r2, prune, &mixed, &touched, &fm);
             full(c0, fm & ~mixed, len);
-            if (mixed) stage_union(L, C.pts, c0, m, mixed, len, sweep);
+            if (mixed) stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, 1, r, r2, sweep);
         }
     };
     traverse(L, C.nodes, C.child, accept, batches);
@@ -624,7 +641,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 // contained for my segment and not swept: count the whole node
                 for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
                 if (!mixed) continue;
-                stage_union(L, C.pts, c0, m, mixed, len, [&](uint32_t n) {
+                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, [&](uint32_t n) {
                     uint32_t t = 0;
                     for (; t + 4 <= n; t += 4) {
                         const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
@@ -732,7 +749,7 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
             uint64_t mixed, touched, full;
             const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
             if (!touched) continue;
-            stage_union(L, C.pts, c0, m, touched, len, [&](uint32_t n) {
+            stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, [&](uint32_t n) {
                 for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
                     flush(kRowCap - kChunk);
                     const uint32_t te = min(n, t0 + kChunk);
