@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--points", type=int, default=10_000_000)
-    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=100_000, help="queries per (kernel, r) for the oracle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
@@ -462,7 +462,7 @@ def main():
         from paper_2603_06771_amd import rocprof_summary
         rec = json.load(open(os.path.join(ROOT, "profiles", "k_radius_fill_lidar10M_traffic.json")))
         src = os.path.join(ROOT, "paper_2603_06771_amd", "csrc", "search.hip")
-        if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 16 and n == 10_000_000:
+        if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 64 and n == 10_000_000:
             traffic = rec["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
