@@ -289,13 +289,13 @@ __device__ __forceinline__ uint64_t wave_or(uint64_t v) {
 }
 
 // Stages the points of the batch candidates [c0, c0 + m) selected by `need`
-// (bit i: candidate c0 + i), in candidate order, kStage points per round, and
-// for every round calls body(count): L.pts[0..count) are the points and
-// L.owner[] their candidate within the batch.  A candidate larger than the
-// staging area spans several rounds.
-template <typename Body>
+// (bit i: candidate c0 + i), in candidate order, up to kStage points per
+// round, and for every round calls body(count): L.pts[0..count) are the
+// points and L.owner[] their candidate within the batch.  Points for which
+// keep(point) is false are dropped while staging (lane = point).
+template <typename Keep, typename Body>
 __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
-                                             Body body) {
+                                             Keep keep, Body body) {
     const int lane = lane_id();
     uint32_t sz = 0;
     if (lane < m && ((need >> lane) & 1ull)) sz = L.cend[c0 + lane] - L.cbeg[c0 + lane];
@@ -303,11 +303,14 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
     L.cincl[lane] = incl;
     const uint32_t total = __shfl(incl, kWave - 1);
     __syncthreads();
-    for (uint32_t done = 0; done < total; done += kStage) {
-        const uint32_t cnt = min(static_cast<uint32_t>(kStage), total - done);
-        for (uint32_t t = lane; t < cnt; t += kWave) {
-            const uint32_t p = done + t;
-            int lo = 0, hi = m - 1;  // first candidate whose inclusive end exceeds p
+    uint32_t kept = 0;  // the same in every lane
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t p = base + lane;
+        bool k = false;
+        float4 v;
+        int lo = 0;
+        if (p < total) {
+            int hi = m - 1;  // first candidate whose inclusive end exceeds p
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (L.cincl[mid] > p)
@@ -316,12 +319,22 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
                     lo = mid + 1;
             }
             const uint32_t first = lo > 0 ? L.cincl[lo - 1] : 0u;
-            L.pts[t] = pts[L.cbeg[c0 + lo] + (p - first)];
-            L.owner[t] = static_cast<uint8_t>(lo);
+            v = pts[L.cbeg[c0 + lo] + (p - first)];
+            k = keep(v);
         }
-        __syncthreads();
-        body(cnt);
-        __syncthreads();
+        const uint64_t km = ballot(k);
+        if (k) {
+            const uint32_t at = kept + rank_below(km);
+            L.pts[at] = v;
+            L.owner[at] = static_cast<uint8_t>(lo);
+        }
+        kept += static_cast<uint32_t>(__popcll(km));
+        if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
+            __syncthreads();
+            body(kept);
+            __syncthreads();
+            kept = 0;
+        }
     }
 }
 
@@ -1037,7 +1050,19 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
                 }
                 const uint64_t need = wave_or(lm);
                 if (!need) continue;
-                stage_rounds(L, C.pts, c0, m, need, [&](uint32_t cnt) {
+                // a point farther from a segment box than the segment's bound
+                // is beyond the bound of each of its lanes (gap test, exact)
+                auto reach = [&](const float4 &v) {
+                    sfc_node b;
+                    b.lo[0] = b.hi[0] = v.x;
+                    b.lo[1] = b.hi[1] = v.y;
+                    b.lo[2] = b.hi[2] = v.z;
+                    bool hit = false;
+                    for (int sg = 0; sg < nseg; ++sg)
+                        hit = hit || group_may_hit<SFC_SPHERE>(b, &L.seg[sg][0], &L.seg[sg][3], 0.0f, s_segr2[sg]);
+                    return hit;
+                };
+                stage_rounds(L, C.pts, c0, m, need, reach, [&](uint32_t cnt) {
                     for (uint32_t t = 0; t < cnt; ++t) {
                         const float4 p = L.pts[t];
                         const uint32_t o = L.owner[t];
