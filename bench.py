@@ -243,7 +243,7 @@ def bench_served(args):
 
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     sizes = datagen.served_sizes(args.served_clouds, seed=datagen.SEED_SERVED)
-    res = serve.Resident(budget_bytes=160 << 30, curve="hilbert", leaf_size=32)
+    res = serve.Resident(budget_bytes=160 << 30, curve="hilbert", leaf_size=64)
     t0 = time.perf_counter()
     build_s = 0.0
     group = 16

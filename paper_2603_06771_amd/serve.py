@@ -42,7 +42,7 @@ KMAX = 32
 class Resident:
     """Clouds and their octrees resident in device memory."""
 
-    def __init__(self, budget_bytes: int, curve="hilbert", bits: int = 21, leaf_size: int = 32):
+    def __init__(self, budget_bytes: int, curve="hilbert", bits: int = 21, leaf_size: int = 64):
         self.budget = int(budget_bytes)
         self.curve = curve
         self.bits = bits
