@@ -1177,15 +1177,17 @@ __device__ __forceinline__ void knn_one(KnnOneLds &L, const SearchCloud &C, cons
             }
             __syncthreads();
         });
-    if (cnt > k) keep_k_smallest(L, cnt, k);
+    // at most one key per lane: rank every key against the others and keep
+    // ranks below k; more keys than lanes are cut back to the k best first
+    if (cnt > kWave) keep_k_smallest(L, cnt, k);
     const int64_t mine = lane < cnt ? L.buf[lane] : INT64_MAX;
     int rank = 0;
     for (int j = 0; j < cnt; ++j) rank += readlane_u64(static_cast<uint64_t>(mine), j) < static_cast<uint64_t>(mine);
-    if (lane < cnt) {
+    if (lane < cnt && rank < k) {
         oi[rank] = static_cast<uint32_t>(static_cast<uint64_t>(mine));
         od[rank] = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(mine) >> 32));
     }
-    for (int i = cnt + lane; i < kstride; i += kWave) {
+    for (int i = (cnt < k ? cnt : k) + lane; i < kstride; i += kWave) {
         oi[i] = 0xFFFFFFFFu;
         od[i] = INFINITY;
     }
@@ -1231,6 +1233,8 @@ __global__ __launch_bounds__(64) void k_knn_spread(SearchArgs a) {
     }
 }
 
+constexpr int kQueryKeyBits = 30;
+
 // External queries in curve order: the code of every query in its cloud's
 // frame (same grid of one wave per 64 rows as the searches) ...
 __global__ __launch_bounds__(64) void k_query_keys(SearchArgs a, uint64_t *__restrict__ keys,
@@ -1241,7 +1245,11 @@ __global__ __launch_bounds__(64) void k_query_keys(SearchArgs a, uint64_t *__res
     const int64_t lr = (g - C.g0) * kWave + lane_id();
     if (lr >= C.nq) return;
     const int64_t row = C.q_offset + lr;
-    keys[row] = point_key(a.queries[3 * row], a.queries[3 * row + 1], a.queries[3 * row + 2], *C.frame);
+    // the leading 30 bits of the code (10 levels: cells of 2^-10 of the
+    // frame) order the queries well enough and need 4 sort passes, not 8
+    const sfc_frame f = *C.frame;
+    const int drop = 3 * f.bits > kQueryKeyBits ? 3 * f.bits - kQueryKeyBits : 0;
+    keys[row] = point_key(a.queries[3 * row], a.queries[3 * row + 1], a.queries[3 * row + 2], f) >> drop;
     perm[row] = static_cast<uint32_t>(row);
 }
 
@@ -1392,8 +1400,8 @@ int order_queries(SearchArgs &a, const SearchWs &w, hipStream_t s) {
         SFC_LAUNCH_CHECK("k_entry_starts");
     }
     bool in_alt = false;
-    const int rc = radix_sort_pairs(w.keys, w.perm, w.keys_alt, w.perm_alt, a.nq_total, nullptr, 63, w.radix, s,
-                                    &in_alt, a.B > 1 ? w.starts : nullptr, a.B);
+    const int rc = radix_sort_pairs(w.keys, w.perm, w.keys_alt, w.perm_alt, a.nq_total, nullptr, kQueryKeyBits,
+                                    w.radix, s, &in_alt, a.B > 1 ? w.starts : nullptr, a.B);
     if (rc) return rc;
     a.qperm = in_alt ? w.perm_alt : w.perm;
     return SFC_OK;

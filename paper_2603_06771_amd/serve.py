@@ -290,9 +290,9 @@ class Server:
                     e.r = float(r.radius)
                     e.q_offset, e.nq = spans[r.id]
                 head = (len(rad), s.table_r, _ptr(s.qr), nq_r, _ptr(s.counts), _ptr(s.offsets))
-                B.check(L.radius_search_batched(*head, None, 0, 0, _ptr(s.ws), ctypes.byref(need), sp), "count")
-                B.check(L.radius_search_batched(*head, _ptr(s.indices), s.indices.numel(), B.REUSE_COUNTS, _ptr(s.ws),
-                                                ctypes.byref(need), sp), "fill")
+                # count, scan and fill in one call (the fill writes only if the slot's buffer holds the total)
+                B.check(L.radius_search_batched(*head, _ptr(s.indices), s.indices.numel(), 0, _ptr(s.ws),
+                                                ctypes.byref(need), sp), "radius")
                 s.total_host.copy_(s.offsets[nq_r:nq_r + 1], non_blocking=True)
             if knn:
                 nq_k = 0
