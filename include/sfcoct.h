@@ -234,6 +234,20 @@ int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, 
 int knn_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, int kstride,
                        uint32_t *idx, float *d2, void *ws, size_t *ws_bytes, void *stream);
 
+/* Section 5.2: the kNN locality histogram of the tree's stored order.  For
+ * the query stored at position rows[r] (rows == NULL: position r) and each of
+ * its neighbours idx[r * kstride + t], t < k (original indices, as
+ * knn_search returns them; entries >= n are padding and skipped), let
+ * d = |rows[r] - pos| with pos the neighbour's stored position (the inverse of
+ * tree->perm).  hist[d] (tree->n entries, u32, overwritten) counts the pairs.
+ * stats (8 doubles, device) receives: total pairs, mean d, standard deviation,
+ * Fisher-Pearson skewness G1 = E[((d - mean) / sd)^3], the quartiles Q1, Q2,
+ * Q3 (smallest d whose cumulative count reaches 1/4, 1/2, 3/4 of the total)
+ * and the largest d.  The statistics are summed in a fixed order (the same
+ * bits on every run).  nq * k must stay below 2^32 (SFC_ENOTSUP). */
+int knn_locality(const sfc_octree *tree, const uint32_t *rows, int64_t nq, const uint32_t *idx, int k, int kstride,
+                 uint32_t *hist, double *stats, void *ws, size_t *ws_bytes, void *stream);
+
 /* Serving helper (not an operation of the paper): assembles a query batch
  * from point ids.  out[3i .. 3i+2] = xyz[3 rows[i] .. 3 rows[i] + 2] for
  * i < n, where xyz holds n_points points (AoS, 3 floats each); a row id

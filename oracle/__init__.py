@@ -5,8 +5,9 @@ CPU-baseline leg of the benchmark may import this package; the GPU library
 never does and shares no code with it.
 
 The arithmetic lives in ``oracle.c`` (plain C, fp32 expressions evaluated as
-written with contraction off); this module only marshals numpy arrays through
-ctypes.  Each wrapper names the part of the paper it follows.
+written with contraction off); this module marshals numpy arrays through
+ctypes, and computes the kNN locality histogram (integer counting and fp64
+moments) in numpy.  Each function names the part of the paper it follows.
 """
 from __future__ import annotations
 
@@ -273,3 +274,40 @@ def knn(xyz, queries, k: int, h: float | None = None):
         ext = float(np.max(xyz.max(0) - xyz.min(0))) if xyz.shape[0] else 1.0
         h = max(ext * (k / n) ** (1.0 / 3.0), ext / 1024.0, 1e-6)
     return Grid(xyz, h, 3).knn(queries, k)
+
+
+def locality_histogram(perm, knn_idx, rows=None):
+    """Section 5.2, the kNN locality histogram: H_k(d) counts the pairs (i, j)
+    with j among the k nearest neighbours of the point stored at position i
+    and |i - j| = d, positions in the stored (sorted) order.
+
+    perm[i] is the original index of the point at position i; knn_idx[r] holds
+    the original indices of the neighbours of the query at position rows[r]
+    (rows = 0 .. len(knn_idx) - 1 when None); 0xFFFFFFFF entries (k beyond the
+    cloud) are skipped.  Returns (H, stats): H int64 of length n; stats total,
+    mean, std, g1 (Fisher-Pearson skewness E[((d - mean) / std)^3]), q1 / q2 /
+    q3 (smallest d whose cumulative count reaches 1/4, 1/2, 3/4 of the total)
+    and max, in fp64."""
+    perm = np.asarray(perm).astype(np.int64)
+    n = perm.size
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    idx = np.asarray(knn_idx).astype(np.int64)
+    rows = np.arange(idx.shape[0], dtype=np.int64) if rows is None else np.asarray(rows).astype(np.int64)
+    valid = idx != 0xFFFFFFFF
+    d = np.abs(rows[:, None] - pos[np.where(valid, idx, 0)])[valid]
+    H = np.bincount(d, minlength=n).astype(np.int64)
+    total = int(H.sum())
+    dv = np.arange(n, dtype=np.float64)
+    stats = {"total": float(total), "mean": 0.0, "std": 0.0, "g1": 0.0, "q1": 0.0, "q2": 0.0, "q3": 0.0,
+             "max": float(d.max()) if d.size else 0.0}
+    if total:
+        mean = float((H * dv).sum() / total)
+        var = float((H * (dv - mean) ** 2).sum() / total)
+        std = var ** 0.5
+        stats["mean"], stats["std"] = mean, std
+        stats["g1"] = float((H * ((dv - mean) / std) ** 3).sum() / total) if std > 0 else 0.0
+        cum = np.cumsum(H)
+        for name, q in (("q1", 1), ("q2", 2), ("q3", 3)):
+            stats[name] = float(np.searchsorted(cum, (q * total + 3) // 4))
+    return H, stats

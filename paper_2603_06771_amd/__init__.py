@@ -14,8 +14,8 @@ from dataclasses import dataclass
 from . import _binding as B
 
 __all__ = ["encode_sfc", "build_linear_octree", "radius_search", "radius_count", "radius_fill", "knn_search", "Octree",
-           "Batch", "build_batch", "radius_search_batched", "knn_search_batched", "CURVES", "KERNELS",
-           "library_path"]
+           "Batch", "build_batch", "radius_search_batched", "knn_search_batched", "knn_locality", "choose_curve",
+           "CURVES", "KERNELS", "library_path"]
 
 CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
 KERNELS = {"sphere": B.SPHERE, "circle": B.CIRCLE, "cube": B.CUBE, "square": B.SQUARE}
@@ -389,3 +389,56 @@ def knn_search_batched(batch: Batch, queries=None, q_sizes=None, k=8, kstride: i
     ws = _ws(torch, need.value)
     B.check(L.knn_search_batched(*head, _ptr(ws), ctypes.byref(need), _stream(torch)), "knn_search_batched")
     return idx, d2
+
+
+# ------------------------------------------------------ locality (Section 5.2)
+LOCALITY_STATS = ("total", "mean", "std", "g1", "q1", "q2", "q3", "max")
+
+
+def knn_locality(tree: Octree, k: int = 8, rows=None, sample: float | None = None, seed: int = 0):
+    """Section 5.2: the kNN locality histogram of the tree's stored order.
+    rows: stored positions of the query points (default all points); with
+    `sample`, a seeded random fraction of the points (the subset estimate).
+    Returns (hist int32 [n], stats dict: total, mean, std, g1, q1, q2, q3,
+    max)."""
+    import numpy as np
+    torch = _torch()
+    L = B.load()
+    n = tree.n
+    if sample is not None:
+        m = max(1, min(n, int(round(float(sample) * n))))
+        rows = np.sort(np.random.default_rng(seed).choice(n, m, replace=False))
+    if rows is None:
+        idx, _ = knn_search(tree, None, k)
+        rows_t, nq = None, n
+    else:
+        rows_t = torch.as_tensor(np.asarray(rows, dtype=np.int64)).cuda()
+        queries = tree.points()[rows_t, :3].contiguous()
+        idx, _ = knn_search(tree, queries, k)
+        rows_t = rows_t.to(torch.int32)
+        nq = int(rows_t.numel())
+    hist = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    stats = torch.empty(8, dtype=torch.float64, device="cuda")
+    need = ctypes.c_size_t(0)
+    args = (ctypes.byref(tree.view), _ptr(rows_t), nq, _ptr(idx), int(k), int(k), _ptr(hist), _ptr(stats))
+    B.check(L.knn_locality(*args, None, ctypes.byref(need), None), "knn_locality(size)")
+    ws = _ws(torch, need.value)
+    B.check(L.knn_locality(*args, _ptr(ws), ctypes.byref(need), _stream(torch)), "knn_locality")
+    return hist, dict(zip(LOCALITY_STATS, stats.cpu().tolist()))
+
+
+def choose_curve(xyz, k: int = 8, sample: float = 0.01, seed: int = 0, bits: int = 21, leaf_size: int = 64):
+    """Section 5.2's use of the histogram: build the cloud along both curves
+    and keep the order whose locality histogram, estimated on a random subset
+    of the points, is the more left-skewed (larger G1).  Returns (curve name,
+    tree, {curve: stats})."""
+    best, stats = None, {}
+    trees = {}
+    for curve in ("morton", "hilbert"):
+        t = build_linear_octree(xyz, curve, bits, leaf_size)
+        _, st = knn_locality(t, k, sample=sample, seed=seed)
+        stats[curve] = st
+        trees[curve] = t
+        if best is None or st["g1"] > stats[best]["g1"]:
+            best = curve
+    return best, trees[best], stats
