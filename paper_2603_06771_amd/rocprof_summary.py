@@ -3,6 +3,7 @@
     python -m paper_2603_06771_amd.rocprof_summary stats <kernel_stats.csv>
     python -m paper_2603_06771_amd.rocprof_summary trace <kernel_trace.csv> <kernel-name> [min_us]
     python -m paper_2603_06771_amd.rocprof_summary sq <counter_collection.csv> <kernel-name>
+    python -m paper_2603_06771_amd.rocprof_summary l2 <counter_collection.csv> <kernel-name>
     python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> [kernel-substring]
 
@@ -74,6 +75,23 @@ def sq(path: str, kernel: str) -> str:
     return "\n".join(out)
 
 
+def l2(path: str, kernel: str) -> str:
+    """Per-dispatch L2 hit rate of `kernel` from TCC_HIT / TCC_MISS."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Kernel_Name"].split("(")[0].split("::")[-1] != kernel:
+            continue
+        d = per.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"].replace("_sum", "")] = float(r["Counter_Value"])
+        d["dur_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    out = [f"{'dispatch':>8s} {'dur_us':>9s} {'hits':>12s} {'misses':>12s} {'hit_rate':>9s}"]
+    for dsp in sorted(per):
+        d = per[dsp]
+        h, m = d.get("TCC_HIT", 0.0), d.get("TCC_MISS", 0.0)
+        out.append(f"{dsp:8d} {d['dur_us']:9.0f} {h:12.0f} {m:12.0f} {h / max(h + m, 1.0):9.3f}")
+    return "\n".join(out)
+
+
 def _per_dispatch(path: str, counter: str):
     rows = []
     for r in csv.DictReader(open(path)):
@@ -138,6 +156,8 @@ def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, m
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+    elif sys.argv[1] == "l2":
+        print(l2(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "sq":
         print(sq(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "trace":
