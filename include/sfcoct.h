@@ -166,6 +166,26 @@ int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int 
                   uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
                   uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
 
+/* Section 5.1, the neighboursStruct form of radius_search: the same
+ * neighbour set per query, split into the ranges of sorted positions of the
+ * octree nodes that lie entirely inside the neighbourhood and the individual
+ * points of the nodes it overlaps only partly (original indices).  Ranges and
+ * points of a row are disjoint; the range [b, e) stands for the points at
+ * sorted positions b .. e - 1 (tree->perm gives their original indices).
+ *   rcounts [nq], roffsets [nq+1]: ranges per row and their row starts
+ *   ranges  [2 * rcapacity]: (begin, end) pairs, or NULL for counts only
+ *   pcounts [nq], poffsets [nq+1], points [pcapacity]: the individual points
+ *           (points must be NULL exactly when ranges is)
+ * Both buffers are written only if both totals fit (checked on the device).
+ * flags: SFC_REUSE_COUNTS, SFC_NO_PRUNE (no ranges: every point listed),
+ * SFC_QUERIES_ORDERED, as for radius_search.  Queries are handled 64 at a time
+ * (no one-query-per-wave path), so widely scattered queries are slower than
+ * with radius_search. */
+int radius_search_struct(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
+                         uint32_t *rcounts, uint64_t *roffsets, uint32_t *ranges, uint64_t rcapacity,
+                         uint32_t *pcounts, uint64_t *poffsets, uint32_t *points, uint64_t pcapacity,
+                         uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
+
 /* Section 3.3: the k nearest cloud points of every query, as the k smallest
  * pairs (d2, original index) in lexicographic order, ascending, where d2 is
  * the SPHERE expression above.  Ties in d2 are broken by the smaller index; a

@@ -15,6 +15,7 @@ from . import _binding as B
 
 __all__ = ["encode_sfc", "build_linear_octree", "radius_search", "radius_count", "radius_fill", "knn_search", "Octree",
            "Batch", "build_batch", "radius_search_batched", "knn_search_batched", "knn_locality", "choose_curve",
+           "radius_search_struct",
            "CURVES", "KERNELS", "library_path"]
 
 CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
@@ -442,3 +443,36 @@ def choose_curve(xyz, k: int = 8, sample: float = 0.01, seed: int = 0, bits: int
         if best is None or st["g1"] > stats[best]["g1"]:
             best = curve
     return best, trees[best], stats
+
+
+def radius_search_struct(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, prune: bool = True):
+    """Section 5.1, neighboursStruct: ((rcounts, roffsets, ranges int32 [R, 2]
+    of sorted positions), (pcounts, poffsets, points int32 original indices)).
+    The count pass runs first and the host reads both totals before the fill."""
+    torch = _torch()
+    L = B.load()
+    if queries is not None:
+        queries = _xyz(torch, queries)
+        nq = queries.shape[0]
+    else:
+        nq = tree.n
+    flags = 0 if prune else B.NO_PRUNE
+    rc = torch.empty(nq, dtype=torch.int32, device="cuda")
+    ro = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    pc = torch.empty(nq, dtype=torch.int32, device="cuda")
+    po = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    head = (ctypes.byref(tree.view), _ptr(queries), nq, _code(KERNELS, kernel), float(r), _ptr(rc), _ptr(ro))
+    need = ctypes.c_size_t(0)
+    B.check(L.radius_search_struct(*head, None, 0, _ptr(pc), _ptr(po), None, 0, flags, None, ctypes.byref(need),
+                                   None), "radius_search_struct(size)")
+    ws = _ws(torch, need.value)
+    stream = _stream(torch)
+    B.check(L.radius_search_struct(*head, None, 0, _ptr(pc), _ptr(po), None, 0, flags, _ptr(ws), ctypes.byref(need),
+                                   stream), "radius_search_struct(count)")
+    nr, npt = int(ro[nq].item()), int(po[nq].item())
+    ranges = torch.empty((max(nr, 1), 2), dtype=torch.int32, device="cuda")
+    points = torch.empty(max(npt, 1), dtype=torch.int32, device="cuda")
+    B.check(L.radius_search_struct(*head, _ptr(ranges), nr, _ptr(pc), _ptr(po), _ptr(points), npt,
+                                   flags | B.REUSE_COUNTS, _ptr(ws), ctypes.byref(need), stream),
+            "radius_search_struct(fill)")
+    return (rc, ro, ranges[:nr]), (pc, po, points[:npt])

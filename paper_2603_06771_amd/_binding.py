@@ -21,7 +21,7 @@ REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED = 1, 2, 4
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
            "octree_batch_layout", "build_linear_octree_batched", "radius_search_batched", "knn_search_batched",
-           "knn_locality", "gather_points", "sfc_last_error", "sfc_version")
+           "radius_search_struct", "knn_locality", "gather_points", "sfc_last_error", "sfc_version")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     L.radius_search_batched.argtypes = [I32, CL, P, I64, P, P, P, U64, U32, P, ctypes.POINTER(SZ), P]
     L.knn_search_batched.argtypes = [I32, CL, P, I64, I32, P, P, P, ctypes.POINTER(SZ), P]
     L.gather_points.argtypes = [P, I64, P, I64, P, P]
+    L.radius_search_struct.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, F32, P, P, P, U64, P, P, P, U64, U32,
+                                       P, ctypes.POINTER(SZ), P]
     L.knn_locality.argtypes = [ctypes.POINTER(SfcOctree), P, I64, P, I32, I32, P, P, P, ctypes.POINTER(SZ), P]
     L.sfc_last_error.restype = ctypes.c_char_p
     L.sfc_version.restype = ctypes.c_char_p

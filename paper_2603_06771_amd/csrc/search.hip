@@ -376,6 +376,10 @@ struct SearchArgs {
     float *d2;
     uint32_t *spread;         // [groups] groups left to the one-query-per-wave kernels
     uint32_t *nspread;        // their number
+    uint32_t *rcounts;        // range form: ranges per row
+    const uint64_t *roffsets; // their row starts
+    uint32_t *ranges;         // (begin, end) pairs of sorted positions
+    uint64_t rcapacity;       // pairs the ranges buffer holds
 };
 
 // Query of a lane (position lr in its cloud's rows) and the global row its
@@ -430,6 +434,7 @@ struct RadLds {
     uint32_t cbeg[kCand];    // their point ranges
     uint32_t cend[kCand];
     float4 pts[kStage];
+    uint8_t owner[kStage];  // candidate (within the batch) of each staged point
     uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
     uint32_t clen[kWave];   // sizes of the batch candidates
     float seg[kSegMax][6];
@@ -524,8 +529,9 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
         const uint32_t p = base + lane;
         bool keep = false;
         float4 v;
+        int lo = 0;
         if (p < total) {
-            int lo = 0, hi = m - 1;  // first candidate whose inclusive end exceeds p
+            int hi = m - 1;  // first candidate whose inclusive end exceeds p
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (L.cincl[mid] > p)
@@ -542,7 +548,10 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
             keep = segments_may_hit<KERNEL>(L, nseg, b, r, r2);
         }
         const uint64_t km = ballot(keep);
-        if (keep) L.pts[kept + rank_below(km)] = v;
+        if (keep) {
+            L.pts[kept + rank_below(km)] = v;
+            L.owner[kept + rank_below(km)] = static_cast<uint8_t>(lo);
+        }
         kept += static_cast<uint32_t>(__popcll(km));
         if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
             __syncthreads();
@@ -798,6 +807,150 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
     flush(0);
 }
 
+// ------------------------------------------------------- range output
+// The paper's neighboursStruct form (Section 5.1): per query, the ranges of
+// sorted positions of the nodes that lie entirely inside its neighbourhood,
+// and the individual points of the nodes it overlaps only partly.  Nodes are
+// classified per lane (the lane's own query against each candidate node,
+// exact by the monotonicity argument); the points of a node that is
+// contained for a lane are not tested for that lane, so ranges and points
+// are disjoint and their union is the radius_search set.
+template <int KERNEL>
+__device__ __forceinline__ void struct_body(FillLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg,
+                                            bool fill) {
+    const int lane = lane_id();
+    const int64_t lr = lg * kWave + lane;
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
+    const float r = C.r, r2 = fmul(r, r);
+    const bool prune = !(a.flags & SFC_NO_PRUNE);
+    uint32_t nr = 0, np = 0;
+    if (r > 0.0f) {
+        int sid = 0;
+        const int nseg = make_segments(L, q, 2.0f * r, &sid);
+        uint64_t rpos = 0, rend = 0, gpos = 0, gend = 0;
+        if (fill && q.valid) {
+            rpos = a.roffsets[row];
+            rend = a.roffsets[row + 1];
+            gpos = a.offsets[row];
+            gend = a.offsets[row + 1];
+        }
+        uint32_t nb = 0;
+        uint8_t *myrow = L.rows + lane * (kRowCap + 1);
+        const int half = lane >> 5, hl = lane & 31;
+        auto flush = [&](uint32_t limit) {
+            const bool go = nb > limit;
+            const uint64_t fm = ballot(go);
+            if (!fm) return;
+            const int nf = __popcll(fm);
+            if (go) {
+                const uint64_t room = gend > gpos ? gend - gpos : 0ull;
+                L.meta[lane] = RowFlush{gpos, nb, static_cast<uint32_t>(room < nb ? room : nb)};
+                L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+            }
+            __syncthreads();
+            for (int i = half; i < nf; i += 2) {
+                const int l = L.flist[i];
+                const RowFlush m = L.meta[l];
+                if (static_cast<uint32_t>(hl) < m.lim)
+                    a.indices[m.pos + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+            }
+            if (go) {
+                gpos += nb;
+                nb = 0;
+            }
+            __syncthreads();
+        };
+        auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
+        auto sweep = [&](int ncand) {
+            for (int c0 = 0; c0 < ncand; c0 += kWave) {
+                const int m = min(kWave, ncand - c0);
+                const uint32_t len = lane < m ? L.cend[c0 + lane] - L.cbeg[c0 + lane] : 0u;
+                uint64_t full = 0, mixed = 0;
+                for (int i = 0; i < m; ++i) {
+                    const sfc_node nd = C.nodes[__builtin_amdgcn_readfirstlane(L.cand[c0 + i])];
+                    int cls = q.valid ? classify<KERNEL>(nd, q.x, q.y, q.z, r, r2) : 0;
+                    if (cls == 1 && !prune) cls = 2;
+                    full |= static_cast<uint64_t>(cls == 1) << i;
+                    mixed |= static_cast<uint64_t>(cls == 2) << i;
+                }
+                if (!fill) {
+                    nr += static_cast<uint32_t>(__popcll(full));
+                } else {
+                    for (int i = 0; i < m; ++i) {
+                        if ((full >> i) & 1ull) {
+                            if (rpos < rend) {
+                                a.ranges[2 * rpos] = L.cbeg[c0 + i];
+                                a.ranges[2 * rpos + 1] = L.cend[c0 + i];
+                            }
+                            ++rpos;
+                        }
+                    }
+                }
+                const uint64_t need = wave_or(mixed);
+                if (!need) continue;
+                stage_union<KERNEL>(L, C.pts, c0, m, need, len, nseg, r, r2, [&](uint32_t n) {
+                    if (!fill) {
+                        for (uint32_t t = 0; t < n; ++t)
+                            np += (point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) && ((mixed >> L.owner[t]) & 1ull))
+                                      ? 1u : 0u;
+                        return;
+                    }
+                    for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
+                        flush(kRowCap - kChunk);
+                        const uint32_t te = min(n, t0 + kChunk);
+                        for (uint32_t t = t0; t < te; ++t) {
+                            const bool h = point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) &
+                                           (((mixed >> L.owner[t]) & 1ull) != 0);
+                            myrow[nb] = static_cast<uint8_t>(t);
+                            nb += h ? 1u : 0u;
+                        }
+                    }
+                    flush(0);
+                });
+            }
+        };
+        traverse(L, C.nodes, C.child, accept, sweep);
+    }
+    if (!fill && q.valid) {
+        a.rcounts[row] = nr;
+        a.counts[row] = np;
+    }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_struct_count(SearchArgs a) {
+    __shared__ FillLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lg = g - C.g0;
+    switch (C.kernel) {
+    case SFC_SPHERE: struct_body<SFC_SPHERE>(L, a, C, lg, false); break;
+    case SFC_CIRCLE: struct_body<SFC_CIRCLE>(L, a, C, lg, false); break;
+    case SFC_CUBE: struct_body<SFC_CUBE>(L, a, C, lg, false); break;
+    default: struct_body<SFC_SQUARE>(L, a, C, lg, false); break;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_struct_fill(SearchArgs a) {
+    __shared__ FillLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    // either buffer too small: write nothing
+    if (a.offsets[a.nq_total] > a.capacity || a.roffsets[a.nq_total] > a.rcapacity) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lg = g - C.g0;
+    switch (C.kernel) {
+    case SFC_SPHERE: struct_body<SFC_SPHERE>(L, a, C, lg, true); break;
+    case SFC_CIRCLE: struct_body<SFC_CIRCLE>(L, a, C, lg, true); break;
+    case SFC_CUBE: struct_body<SFC_CUBE>(L, a, C, lg, true); break;
+    default: struct_body<SFC_SQUARE>(L, a, C, lg, true); break;
+    }
+}
+
+namespace {
 }  // namespace
 
 // One wave per group of 64 queries of one cloud; the cloud's kernel selects
@@ -1535,6 +1688,77 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
     a.capacity = capacity;
     a.nq_total = nq;
     return radius_launch(a, tab, (nq + kWave - 1) / kWave, counts, ws, s);
+}
+
+extern "C" int radius_search_struct(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
+                                    uint32_t *rcounts, uint64_t *roffsets, uint32_t *ranges, uint64_t rcapacity,
+                                    uint32_t *pcounts, uint64_t *poffsets, uint32_t *points, uint64_t pcapacity,
+                                    uint32_t flags, void *ws, size_t *ws_bytes, void *stream) {
+    if (!ws_bytes || !tree_ok(tree) || kernel < 0 || kernel > 3 || nq < 0 || !rcounts || !roffsets || !pcounts ||
+        !poffsets || (!queries && nq != tree->n) || std::isnan(r) || std::isinf(r) ||
+        (ranges == nullptr) != (points == nullptr)) {
+        set_error("radius_search_struct: invalid argument");
+        return SFC_EINVAL;
+    }
+    const bool order = wants_order(queries, nq, flags);
+    // two scans: the second scratch follows the search workspace
+    const size_t need = search_ws_bytes(1, nq, true, order) + align_up(scan_ws_bytes(nq), 256);
+    if (!ws) {
+        *ws_bytes = need;
+        return SFC_OK;
+    }
+    if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("radius_search_struct: workspace needs %zu bytes, 256-aligned", need);
+        return SFC_EWORKSPACE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nq == 0 || !(r > 0.0f)) {
+        if (!(flags & SFC_REUSE_COUNTS)) {
+            k_zero_rows<<<grid_for(nq + 1, 256, 4096), 256, 0, s>>>(rcounts, roffsets, nq);
+            SFC_LAUNCH_CHECK("k_zero_rows");
+            k_zero_rows<<<grid_for(nq + 1, 256, 4096), 256, 0, s>>>(pcounts, poffsets, nq);
+            SFC_LAUNCH_CHECK("k_zero_rows");
+        }
+        return SFC_OK;
+    }
+    std::vector<SearchCloud> tab(1, cloud_entry(*tree, 0, nq, 0, kernel, r, 0));
+    SearchArgs a = blank_args();
+    a.queries = queries;
+    a.flags = flags;
+    a.counts = pcounts;
+    a.offsets = poffsets;
+    a.indices = points;
+    a.capacity = pcapacity;
+    a.rcounts = rcounts;
+    a.roffsets = roffsets;
+    a.ranges = ranges;
+    a.rcapacity = rcapacity;
+    a.nq_total = nq;
+    SearchWs w;
+    carve_search_ws(1, nq, true, order, ws, &w);
+    void *scan2 = static_cast<char *>(ws) + search_ws_bytes(1, nq, true, order);
+    a.one = tab[0];
+    a.tab = nullptr;
+    a.B = 1;
+    a.groups = (nq + kWave - 1) / kWave;
+    if (order) {
+        const int rc = order_queries(a, w, s);
+        if (rc) return rc;
+    }
+    const unsigned grid = static_cast<unsigned>(xcd_grid(a.groups));
+    if (!(flags & SFC_REUSE_COUNTS)) {
+        k_struct_count<<<grid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_struct_count");
+        int rc = scan_u32_to_u64(rcounts, nq, roffsets, true, w.scan, s);
+        if (rc) return rc;
+        rc = scan_u32_to_u64(pcounts, nq, poffsets, true, scan2, s);
+        if (rc) return rc;
+    }
+    if (ranges) {
+        k_struct_fill<<<grid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_struct_fill");
+    }
+    return SFC_OK;
 }
 
 extern "C" int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total,
