@@ -195,7 +195,9 @@ int radius_search_struct(const sfc_octree *tree, const float *queries, int64_t n
  *            external queries are reordered along the curve inside the call
  *            (as radius_search without SFC_QUERIES_ORDERED)
  *   idx      [nq*k] output indices;  d2 [nq*k] output squared distances
- * 1 <= k <= 32 (SFC_ENOTSUP above). */
+ * 1 <= k <= 512 (SFC_ENOTSUP above).  k <= 32 keeps each query's list in
+ * registers (64 queries per wave); larger k takes one query per wave with a
+ * candidate buffer in LDS. */
 int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx,
                float *d2, void *ws, size_t *ws_bytes, void *stream);
 
@@ -248,7 +250,7 @@ int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, 
                           uint64_t *offsets, uint32_t *indices, uint64_t capacity, uint32_t flags, void *ws,
                           size_t *ws_bytes, void *stream);
 
-/* k-NN for every cloud of the batch with its own k (<= kstride <= 32): row q
+/* k-NN for every cloud of the batch with its own k (<= kstride <= 512): row q
  * occupies idx / d2 [q * kstride, (q + 1) * kstride); entries past the
  * cloud's k are (0xFFFFFFFF, +inf). */
 int knn_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, int kstride,

@@ -1260,20 +1260,24 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
 // ---------------------------------------------------- k-NN of spread groups
 namespace {
 
-constexpr int kKnnBuf = 256;  // candidate keys held per query before a reduction
+constexpr int kKnnBuf = 256;        // candidate keys held per query (k <= 32)
+constexpr int kKnnBufLarge = 1024;  // the same for k up to kKnnMaxK
+constexpr int kKnnMaxK = 512;
 
+template <int BUF>
 struct KnnOneLds : RadLds {
-    int64_t buf[kKnnBuf];
+    int64_t buf[BUF];
 };
 
 // Keeps the k smallest of the cnt keys in L.buf (keys are distinct: the
 // index is part of them); returns the k-th smallest.  The k-th key is found
 // by bisection on the key value (counting keys <= mid over the wave).
-__device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds &L, int &cnt, int k) {
+template <int BUF>
+__device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds<BUF> &L, int &cnt, int k) {
     const int lane = lane_id();
-    int64_t v[kKnnBuf / kWave];
+    int64_t v[BUF / kWave];
 #pragma unroll
-    for (int i = 0; i < kKnnBuf / kWave; ++i) {
+    for (int i = 0; i < BUF / kWave; ++i) {
         const int e = lane + i * kWave;
         v[i] = e < cnt ? L.buf[e] : INT64_MAX;
     }
@@ -1282,7 +1286,7 @@ __device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds &L, int &cnt, int k
         const int64_t mid = lo + (hi - lo) / 2;
         uint32_t c = 0;
 #pragma unroll
-        for (int i = 0; i < kKnnBuf / kWave; ++i) c += v[i] <= mid ? 1u : 0u;
+        for (int i = 0; i < BUF / kWave; ++i) c += v[i] <= mid ? 1u : 0u;
         if (static_cast<int>(wave_sum_u(c)) >= k)
             hi = mid;
         else
@@ -1291,7 +1295,7 @@ __device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds &L, int &cnt, int k
     __syncthreads();
     int at = 0;
 #pragma unroll
-    for (int i = 0; i < kKnnBuf / kWave; ++i) {
+    for (int i = 0; i < BUF / kWave; ++i) {
         const bool keep = v[i] <= lo;
         const uint64_t m = ballot(keep);
         if (keep) L.buf[at + static_cast<int>(rank_below(m))] = v[i];
@@ -1305,8 +1309,9 @@ __device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds &L, int &cnt, int k
 // k-NN of one query with the whole wave (lane = candidate point): every
 // point with d2 <= tau is a candidate (tau bounds the k-th distance), the
 // buffer is cut back to the k best when it fills, and the final k are ranked
-// by comparing every pair.
-__device__ __forceinline__ void knn_one(KnnOneLds &L, const SearchCloud &C, const Query &q, int k, float tau,
+// by counting, for each kept key, the kept keys below it.
+template <int BUF>
+__device__ __forceinline__ void knn_one(KnnOneLds<BUF> &L, const SearchCloud &C, const Query &q, int k, float tau,
                                         uint32_t *oi, float *od, int kstride) {
     const int lane = lane_id();
     int cnt = 0;
@@ -1316,7 +1321,7 @@ __device__ __forceinline__ void knn_one(KnnOneLds &L, const SearchCloud &C, cons
         L, C, q.x, q.y, q.z, tau < INFINITY ? sqrtf(r2) : INFINITY, r2, false, [](int, uint64_t, uint32_t) {},
         [&](uint32_t n) {
             for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
-                if (cnt + kWave > kKnnBuf) {
+                if (cnt + kWave > BUF) {
                     const int64_t kth = keep_k_smallest(L, cnt, k);
                     bound = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(kth) >> 32));
                 }
@@ -1330,27 +1335,68 @@ __device__ __forceinline__ void knn_one(KnnOneLds &L, const SearchCloud &C, cons
             }
             __syncthreads();
         });
-    // at most one key per lane: rank every key against the others and keep
-    // ranks below k; more keys than lanes are cut back to the k best first
-    if (cnt > kWave) keep_k_smallest(L, cnt, k);
-    const int64_t mine = lane < cnt ? L.buf[lane] : INT64_MAX;
-    int rank = 0;
-    for (int j = 0; j < cnt; ++j) rank += readlane_u64(static_cast<uint64_t>(mine), j) < static_cast<uint64_t>(mine);
-    if (lane < cnt && rank < k) {
-        oi[rank] = static_cast<uint32_t>(static_cast<uint64_t>(mine));
-        od[rank] = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(mine) >> 32));
+    // more keys than lanes (or than k) are cut back to the k best first
+    if (cnt > (k < kWave ? kWave : k)) keep_k_smallest(L, cnt, k);
+    const int have = cnt < k ? cnt : k;
+    for (int e0 = 0; e0 < cnt; e0 += kWave) {
+        const int e = e0 + lane;
+        const int64_t mine = e < cnt ? L.buf[e] : INT64_MAX;
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += L.buf[j] < mine ? 1 : 0;
+        if (e < cnt && rank < k) {
+            oi[rank] = static_cast<uint32_t>(static_cast<uint64_t>(mine));
+            od[rank] = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(mine) >> 32));
+        }
     }
-    for (int i = (cnt < k ? cnt : k) + lane; i < kstride; i += kWave) {
+    for (int i = have + lane; i < kstride; i += kWave) {
         oi[i] = 0xFFFFFFFFu;
         od[i] = INFINITY;
     }
     __syncthreads();
 }
 
+// tau for one query with the whole wave: the k-th smallest d2 over the
+// min(n, max(64, 2k)) curve points around the query's curve position (lane j
+// takes points j, j + 64, ...), a bound of the k-th distance
+template <int PER>
+__device__ __forceinline__ float window_tau(const SearchArgs &a, const SearchCloud &C, const Query &q, int64_t lr,
+                                            int k) {
+    if (C.n < k) return INFINITY;
+    int64_t want = 2 * static_cast<int64_t>(k);
+    if (want < kWave) want = kWave;
+    if (want > static_cast<int64_t>(PER) * kWave) want = static_cast<int64_t>(PER) * kWave;
+    const int64_t w = C.n < want ? C.n : want;
+    int64_t pos = lr;
+    if (a.queries) pos = lower_bound_keys<uint64_t>(C.keys, C.n, point_key(q.x, q.y, q.z, *C.frame));
+    int64_t s0 = pos - w / 2;
+    if (s0 > C.n - w) s0 = C.n - w;
+    if (s0 < 0) s0 = 0;
+    const int lane = lane_id();
+    uint32_t db[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t j = lane + static_cast<int64_t>(i) * kWave;
+        db[i] = j < w ? __float_as_uint(dist2(C.pts[s0 + j], q.x, q.y, q.z)) : 0xFFFFFFFFu;
+    }
+    uint32_t lo = 0u, hi = 0x7F800000u;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) c += db[i] <= mid ? 1u : 0u;
+        if (static_cast<int>(wave_sum_u(c)) >= k)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return __uint_as_float(lo);
+}
+
 }  // namespace
 
+// Deferred (spread) k-NN groups: one query per wave.
 __global__ __launch_bounds__(64) void k_knn_spread(SearchArgs a) {
-    __shared__ KnnOneLds L;
+    __shared__ KnnOneLds<kKnnBuf> L;
     const int64_t total = static_cast<int64_t>(*a.nspread) * kWave;
     for (int64_t j = xcd_item(blockIdx.x, gridDim.x); j < total; j += gridDim.x) {
         const int64_t g = a.spread[j / kWave];
@@ -1359,30 +1405,25 @@ __global__ __launch_bounds__(64) void k_knn_spread(SearchArgs a) {
         if (lr >= C.nq) continue;
         int64_t row;
         const Query q = lane_query(a, C, lr, &row);
-        // tau: the k-th smallest d2 over the 64 curve points around the
-        // query (lane j takes one of them), a bound of the k-th distance
-        const int k = C.k;
-        float tau = INFINITY;
-        if (C.n >= k) {
-            const int64_t w = C.n < kWave ? C.n : kWave;
-            int64_t pos = lr;
-            if (a.queries) pos = lower_bound_keys<uint64_t>(C.keys, C.n, point_key(q.x, q.y, q.z, *C.frame));
-            int64_t s0 = pos - w / 2;
-            if (s0 > C.n - w) s0 = C.n - w;
-            if (s0 < 0) s0 = 0;
-            const int lane = lane_id();
-            const uint32_t db = lane < w ? __float_as_uint(dist2(C.pts[s0 + lane], q.x, q.y, q.z)) : 0xFFFFFFFFu;
-            uint32_t lo = 0u, hi = 0x7F800000u;
-            while (lo < hi) {
-                const uint32_t mid = lo + (hi - lo) / 2;
-                if (__popcll(ballot(db <= mid)) >= k)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            tau = __uint_as_float(lo);
-        }
-        knn_one(L, C, q, k, tau, a.idx + row * a.kstride, a.d2 + row * a.kstride, a.kstride);
+        const float tau = window_tau<1>(a, C, q, lr, C.k);
+        knn_one(L, C, q, C.k, tau, a.idx + row * a.kstride, a.d2 + row * a.kstride, a.kstride);
+    }
+}
+
+// k above what the registers of the group kernel hold: every query with
+// the one-query-per-wave scheme.
+__global__ __launch_bounds__(64) void k_knn_large(SearchArgs a) {
+    __shared__ KnnOneLds<kKnnBufLarge> L;
+    const int64_t total = a.groups * kWave;
+    for (int64_t j = xcd_item(blockIdx.x, gridDim.x); j < total; j += gridDim.x) {
+        const int64_t g = j / kWave;
+        const SearchCloud C = group_cloud(a, g);
+        const int64_t lr = (g - C.g0) * kWave + (j % kWave);
+        if (lr >= C.nq) continue;
+        int64_t row;
+        const Query q = lane_query(a, C, lr, &row);
+        const float tau = window_tau<2 * kKnnMaxK / kWave>(a, C, q, lr, C.k);
+        knn_one(L, C, q, C.k, tau, a.idx + row * a.kstride, a.d2 + row * a.kstride, a.kstride);
     }
 }
 
@@ -1629,6 +1670,12 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
         if (rc) return rc;
     }
     const unsigned grid = static_cast<unsigned>(xcd_grid(groups));
+    const unsigned qgrid = static_cast<unsigned>(xcd_grid(std::min<int64_t>(groups * kWave, 1 << 16)));
+    if (kmax > 32) {
+        k_knn_large<<<qgrid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_knn_large");
+        return SFC_OK;
+    }
     a.spread = w.spread;
     a.nspread = w.nspread;
     k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
@@ -1640,7 +1687,7 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
     else
         k_knn<32><<<grid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn");
-    k_knn_spread<<<static_cast<unsigned>(xcd_grid(std::min<int64_t>(groups * kWave, 1 << 16))), 64, 0, s>>>(a);
+    k_knn_spread<<<qgrid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn_spread");
     return SFC_OK;
 }
@@ -1797,8 +1844,8 @@ extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t 
         set_error("knn_search: invalid argument");
         return SFC_EINVAL;
     }
-    if (k > 32) {
-        set_error("knn_search: k = %d above 32 is not supported", k);
+    if (k > kKnnMaxK) {
+        set_error("knn_search: k = %d above %d is not supported", k, kKnnMaxK);
         return SFC_ENOTSUP;
     }
     const size_t need = search_ws_bytes(1, nq, false, wants_order(queries, nq, 0));
@@ -1826,8 +1873,8 @@ extern "C" int knn_search_batched(int B, const sfc_cloud *clouds, const float *q
         set_error("knn_search_batched: invalid argument");
         return SFC_EINVAL;
     }
-    if (kstride > 32) {
-        set_error("knn_search_batched: kstride = %d above 32 is not supported", kstride);
+    if (kstride > kKnnMaxK) {
+        set_error("knn_search_batched: kstride = %d above %d is not supported", kstride, kKnnMaxK);
         return SFC_ENOTSUP;
     }
     std::vector<SearchCloud> tab;

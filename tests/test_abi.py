@@ -99,7 +99,7 @@ def test_search_argument_validation(lib):
                              ctypes.byref(need), None) == B.SFC_EINVAL
     assert lib.radius_search(ctypes.byref(view), None, 10, 0, 1.0, fake, fake, None, 0, 0, None,
                              ctypes.byref(need), None) == B.SFC_OK and need.value > 0
-    assert lib.knn_search(ctypes.byref(view), None, 10, 33, fake, fake, None, ctypes.byref(need), None) \
+    assert lib.knn_search(ctypes.byref(view), None, 10, 513, fake, fake, None, ctypes.byref(need), None) \
         == B.SFC_ENOTSUP
     assert lib.knn_search(ctypes.byref(view), None, 10, 0, fake, fake, None, ctypes.byref(need), None) \
         == B.SFC_EINVAL
@@ -133,7 +133,7 @@ def test_batched_host_validation(lib):
     fake = ctypes.c_void_p(256)
     assert lib.radius_search_batched(nb, cl, None, 1050, fake, fake, None, 0, 0, None, ctypes.byref(need),
                                      None) == B.SFC_EINVAL
-    assert lib.knn_search_batched(nb, cl, None, 1050, 33, fake, fake, None, ctypes.byref(need), None) \
+    assert lib.knn_search_batched(nb, cl, None, 1050, 513, fake, fake, None, ctypes.byref(need), None) \
         == B.SFC_ENOTSUP
 
 

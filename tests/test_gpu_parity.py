@@ -241,6 +241,25 @@ def test_knn_sparse_queries(sfc, k):
     _knn_case(sfc, dup, "morton", 8, k, queries=dup[np.sort(rng.choice(dup.shape[0], 500, replace=False))])
 
 
+@pytest.mark.parametrize("k", [33, 64, 100, 300, 512])
+def test_knn_large_k(sfc, k):
+    # k above the register lists: one query per wave, LDS candidate buffer
+    pts = _cloud("lidar", 20000, seed=26)
+    announce(f"knn large k={k}")
+    _knn_case(sfc, pts, "hilbert", 64, k)
+    rng = np.random.default_rng(27)
+    lo, hi = pts.min(0), pts.max(0)
+    q = (lo + (hi - lo) * rng.uniform(-0.05, 1.05, (700, 3))).astype(np.float32)
+    announce(f"knn large k={k}, external queries")
+    _knn_case(sfc, pts, "morton", 16, k, queries=q)
+
+
+def test_knn_large_k_small_cloud_and_ties(sfc):
+    announce("knn large k, k > n and duplicates")
+    _knn_case(sfc, _cloud("uniform", 150, seed=28), "hilbert", 8, 200)
+    _knn_case(sfc, _cloud("dup", 5000, seed=29), "morton", 8, 96)
+
+
 def test_knn_duplicates_ties(sfc):
     pts = _cloud("dup", 20000, seed=13)
     for k in (4, 16, 32):
