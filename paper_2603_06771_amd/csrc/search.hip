@@ -511,12 +511,13 @@ __device__ __forceinline__ uint32_t classify_segments(Lds &L, const sfc_node *__
 
 // Stages the points of the batch candidates [c0, c0 + m) selected by `need`
 // (bit i: candidate c0 + i), in candidate order, and calls body(count) with
-// L.pts[0..count) filled, up to kStage points per round.  Points that no
+// L.pts[0..count) filled (and, with OWNER, L.owner[] the candidate of each
+// point within the batch), up to kStage points per round.  Points that no
 // query of any segment can reach are dropped while staging (lane = point,
 // the conservative gap test of the segment boxes, exact by the monotonicity
 // argument): a point outside every grown segment box is a neighbour of none
 // of the wave's queries, so only the sweep's work changes, never a result.
-template <int KERNEL, typename Lds, typename Body>
+template <int KERNEL, bool OWNER = false, typename Lds, typename Body>
 __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
                                             uint32_t len, int nseg, float r, float r2, Body body) {
     const int lane = lane_id();
@@ -550,7 +551,7 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
         const uint64_t km = ballot(keep);
         if (keep) {
             L.pts[kept + rank_below(km)] = v;
-            L.owner[kept + rank_below(km)] = static_cast<uint8_t>(lo);
+            if constexpr (OWNER) L.owner[kept + rank_below(km)] = static_cast<uint8_t>(lo);
         }
         kept += static_cast<uint32_t>(__popcll(km));
         if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
@@ -889,7 +890,7 @@ __device__ __forceinline__ void struct_body(FillLds &L, const SearchArgs &a, con
                 }
                 const uint64_t need = wave_or(mixed);
                 if (!need) continue;
-                stage_union<KERNEL>(L, C.pts, c0, m, need, len, nseg, r, r2, [&](uint32_t n) {
+                stage_union<KERNEL, true>(L, C.pts, c0, m, need, len, nseg, r, r2, [&](uint32_t n) {
                     if (!fill) {
                         for (uint32_t t = 0; t < n; ++t)
                             np += (point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) && ((mixed >> L.owner[t]) & 1ull))
