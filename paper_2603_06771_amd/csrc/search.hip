@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstring>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "codes.hpp"
@@ -78,9 +79,9 @@ __device__ __forceinline__ bool point_hit(const float4 &p, float qx, float qy, f
         return fadd(fmul(dx, dx), fmul(dy, dy)) < r2;
     } else if constexpr (KERNEL == SFC_CUBE) {
         const float dz = fsub(p.z, qz);
-        return fabsf(dx) < r && fabsf(dy) < r && fabsf(dz) < r;
+        return (fabsf(dx) < r) & (fabsf(dy) < r) & (fabsf(dz) < r);
     } else {
-        return fabsf(dx) < r && fabsf(dy) < r;
+        return (fabsf(dx) < r) & (fabsf(dy) < r);
     }
 }
 
@@ -112,8 +113,8 @@ __device__ __forceinline__ int classify(const sfc_node &b, float qx, float qy, f
             const float far2 = fadd(fadd(fmul(fx, fx), fmul(fy, fy)), fmul(fz, fz));
             return far2 < r2 ? 1 : 2;
         } else {
-            if (!(nx < r && ny < r && nz < r)) return 0;
-            return (fx < r && fy < r && fz < r) ? 1 : 2;
+            if (!((nx < r) & (ny < r) & (nz < r))) return 0;
+            return ((fx < r) & (fy < r) & (fz < r)) ? 1 : 2;
         }
     } else if constexpr (KERNEL == SFC_CIRCLE) {
         const float near2 = fadd(fmul(nx, nx), fmul(ny, ny));
@@ -121,8 +122,8 @@ __device__ __forceinline__ int classify(const sfc_node &b, float qx, float qy, f
         const float far2 = fadd(fmul(fx, fx), fmul(fy, fy));
         return far2 < r2 ? 1 : 2;
     } else {
-        if (!(nx < r && ny < r)) return 0;
-        return (fx < r && fy < r) ? 1 : 2;
+        if (!((nx < r) & (ny < r))) return 0;
+        return ((fx < r) & (fy < r)) ? 1 : 2;
     }
 }
 
@@ -144,9 +145,9 @@ __device__ __forceinline__ bool group_may_hit(const sfc_node &b, const float *gl
         return fadd(fmul(gx, gx), fmul(gy, gy)) < r2;
     } else if constexpr (KERNEL == SFC_CUBE) {
         const float gz = gap(b.lo[2], b.hi[2], glo[2], ghi[2]);
-        return gx < r && gy < r && gz < r;
+        return (gx < r) & (gy < r) & (gz < r);
     } else {
-        return gx < r && gy < r;
+        return (gx < r) & (gy < r);
     }
 }
 
@@ -223,6 +224,12 @@ __device__ __forceinline__ bool segments_may_hit(const Lds &L, int nseg, const s
     return hit;
 }
 
+// does the LDS layout keep the candidates' ends?
+template <typename T, typename = void>
+struct HasEnds : std::false_type {};
+template <typename T>
+struct HasEnds<T, std::void_t<decltype(std::declval<T &>().cend)>> : std::true_type {};
+
 // Walks the tree; each time the candidate list fills up (or the walk ends)
 // calls sweep(ncand).  accept(node) decides whether the wave keeps a node.
 template <typename Lds, typename Accept, typename Sweep>
@@ -266,7 +273,7 @@ __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ no
             const int at = ncand + static_cast<int>(rank_below(m_c));
             L.cand[at] = node;
             L.cbeg[at] = nd.begin;
-            L.cend[at] = nd.end;
+            if constexpr (HasEnds<Lds>::value) L.cend[at] = nd.end;
             if constexpr (std::is_same<Lds, WaveLds>::value) L.cnode[at] = nd;
         }
         ncand += __popcll(m_c);
@@ -301,7 +308,7 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
     if (lane < m && ((need >> lane) & 1ull)) sz = L.cend[c0 + lane] - L.cbeg[c0 + lane];
     const uint32_t incl = wave_inclusive_sum(sz);
     L.cincl[lane] = incl;
-    const uint32_t total = __shfl(incl, kWave - 1);
+    const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
     __syncthreads();
     uint32_t kept = 0;  // the same in every lane
     for (uint32_t base = 0; base < total; base += kWave) {
@@ -431,26 +438,27 @@ __device__ __forceinline__ SearchCloud group_cloud(const SearchArgs &a, int64_t 
 struct RadLds {
     int stack[kStack];
     int cand[kCand];         // candidate nodes (indices)
-    uint32_t cbeg[kCand];    // their point ranges
-    uint32_t cend[kCand];
+    uint32_t cbeg[kCand];    // their first points
     float4 pts[kStage];
-    uint8_t owner[kStage];  // candidate (within the batch) of each staged point
-    uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
-    uint32_t clen[kWave];   // sizes of the batch candidates
+    union {
+        uint32_t clen[kWave];   // sizes of the batch candidates (read before staging starts)
+        uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
+    };
     float seg[kSegMax][6];
-};
-
-// a row being flushed: global position, entries, entries that fit its slot
-struct RowFlush {
-    uint64_t pos;
-    uint32_t nb;
-    uint32_t lim;
 };
 
 struct FillLds : RadLds {
     uint8_t rows[kWave * (kRowCap + 1)];   // per-query output staging: staged-point slots
-    RowFlush meta[kWave];
+    uint64_t fpos[kWave];                  // rows being flushed: global position
+    uint8_t flim[kWave];                   // and the entries that fit the row's slot
     uint8_t flist[kWave];                  // lanes whose rows are flushed
+};
+
+// the range form also keeps the candidates' ends and records the candidate
+// of every staged point
+struct StructLds : FillLds {
+    uint32_t cend[kCand];
+    uint8_t owner[kStage];
 };
 
 // largest |fp32 difference| between a coordinate of [lo, hi] and one of [glo, ghi]
@@ -473,9 +481,9 @@ __device__ __forceinline__ int classify_box(const sfc_node &b, const float *glo,
         return fadd(fmul(fx, fx), fmul(fy, fy)) < r2 ? 1 : 2;
     } else if constexpr (KERNEL == SFC_CUBE) {
         const float fz = far_gap(b.lo[2], b.hi[2], glo[2], ghi[2]);
-        return (fx < r && fy < r && fz < r) ? 1 : 2;
+        return ((fx < r) & (fy < r) & (fz < r)) ? 1 : 2;
     } else {
-        return (fx < r && fy < r) ? 1 : 2;
+        return ((fx < r) & (fy < r)) ? 1 : 2;
     }
 }
 
@@ -523,7 +531,7 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
     const int lane = lane_id();
     const uint32_t incl = wave_inclusive_sum(((need >> lane) & 1ull) ? len : 0u);
     L.cincl[lane] = incl;
-    const uint32_t total = __shfl(incl, kWave - 1);
+    const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
     __syncthreads();
     uint32_t kept = 0;  // points staged for the next round (the same in every lane)
     for (uint32_t base = 0; base < total; base += kWave) {
@@ -664,7 +672,8 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 // contained for my segment and not swept: count the whole node
                 for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
                 if (!mixed) continue;
-                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, [&](uint32_t n) {
+                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, [&](uint32_t n_) {
+                    const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
                     uint32_t t = 0;
                     for (; t + 4 <= n; t += 4) {
                         const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
@@ -736,6 +745,9 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
     uint32_t nb = 0;
     uint8_t *myrow = L.rows + lane * (kRowCap + 1);
     uint32_t *out = a.indices;
+    // a lane without a query tests against a point at infinity: it never
+    // hits (finite points), so its row stays empty
+    const float qx = q.valid ? q.x : INFINITY, qy = q.valid ? q.y : INFINITY, qz = q.valid ? q.z : INFINITY;
     const int half = lane >> 5, hl = lane & 31;
 
     // Writes out every row holding more than `limit` entries, two rows per
@@ -749,15 +761,17 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         const int nf = __popcll(fm);
         if (go) {
             const uint64_t room = gend > gpos ? gend - gpos : 0ull;
-            L.meta[lane] = RowFlush{gpos, nb, static_cast<uint32_t>(room < nb ? room : nb)};
+            L.fpos[lane] = gpos;
+                L.flim[lane] = static_cast<uint8_t>(room < nb ? room : nb);
             L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
         }
         __syncthreads();
-        for (int i = half; i < nf; i += 2) {
-            const int l = L.flist[i];
-            const RowFlush m = L.meta[l];
-            if (static_cast<uint32_t>(hl) < m.lim)
-                out[m.pos + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+        for (int i0 = 0; i0 < nf; i0 += 2) {
+            const int i = i0 + half;
+            if (i < nf) {
+                const int l = L.flist[i];
+                if (hl < L.flim[l]) out[L.fpos[l] + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+            }
         }
         if (go) {
             gpos += nb;
@@ -772,33 +786,35 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
             uint64_t mixed, touched, full;
             const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
             if (!touched) continue;
-            stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, [&](uint32_t n) {
+            stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, [&](uint32_t n_) {
+                const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
                 for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
                     flush(kRowCap - kChunk);
                     const uint32_t te = min(n, t0 + kChunk);
                     uint32_t t = t0;
+                    uint8_t *w = myrow + nb;  // next free slot
                     for (; t + 4 <= te; t += 4) {
                         const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
-                        const bool h0 = point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) & q.valid;
-                        const bool h1 = point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) & q.valid;
-                        const bool h2 = point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) & q.valid;
-                        const bool h3 = point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) & q.valid;
+                        const bool h0 = point_hit<KERNEL>(p0, qx, qy, qz, r, r2);
+                        const bool h1 = point_hit<KERNEL>(p1, qx, qy, qz, r, r2);
+                        const bool h2 = point_hit<KERNEL>(p2, qx, qy, qz, r, r2);
+                        const bool h3 = point_hit<KERNEL>(p3, qx, qy, qz, r, r2);
                         // each slot is overwritten unless it holds a hit
-                        myrow[nb] = static_cast<uint8_t>(t + 0);
-                        nb += h0 ? 1u : 0u;
-                        myrow[nb] = static_cast<uint8_t>(t + 1);
-                        nb += h1 ? 1u : 0u;
-                        myrow[nb] = static_cast<uint8_t>(t + 2);
-                        nb += h2 ? 1u : 0u;
-                        myrow[nb] = static_cast<uint8_t>(t + 3);
-                        nb += h3 ? 1u : 0u;
+                        *w = static_cast<uint8_t>(t + 0);
+                        w += h0;
+                        *w = static_cast<uint8_t>(t + 1);
+                        w += h1;
+                        *w = static_cast<uint8_t>(t + 2);
+                        w += h2;
+                        *w = static_cast<uint8_t>(t + 3);
+                        w += h3;
                     }
                     for (; t < te; ++t) {
-                        const float4 p = L.pts[t];
-                        const bool h = point_hit<KERNEL>(p, q.x, q.y, q.z, r, r2) & q.valid;
-                        myrow[nb] = static_cast<uint8_t>(t);
-                        nb += h ? 1u : 0u;
+                        const bool h = point_hit<KERNEL>(L.pts[t], qx, qy, qz, r, r2);
+                        *w = static_cast<uint8_t>(t);
+                        w += h;
                     }
+                    nb = static_cast<uint32_t>(w - myrow);
                 }
                 flush(0);  // the rows point into this round's staged points
             });
@@ -817,7 +833,7 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
 // contained for a lane are not tested for that lane, so ranges and points
 // are disjoint and their union is the radius_search set.
 template <int KERNEL>
-__device__ __forceinline__ void struct_body(FillLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg,
+__device__ __forceinline__ void struct_body(StructLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg,
                                             bool fill) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
@@ -846,15 +862,15 @@ __device__ __forceinline__ void struct_body(FillLds &L, const SearchArgs &a, con
             const int nf = __popcll(fm);
             if (go) {
                 const uint64_t room = gend > gpos ? gend - gpos : 0ull;
-                L.meta[lane] = RowFlush{gpos, nb, static_cast<uint32_t>(room < nb ? room : nb)};
+                L.fpos[lane] = gpos;
+                L.flim[lane] = static_cast<uint8_t>(room < nb ? room : nb);
                 L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
             }
             __syncthreads();
             for (int i = half; i < nf; i += 2) {
                 const int l = L.flist[i];
-                const RowFlush m = L.meta[l];
-                if (static_cast<uint32_t>(hl) < m.lim)
-                    a.indices[m.pos + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+                if (hl < L.flim[l])
+                    a.indices[L.fpos[l] + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
             }
             if (go) {
                 gpos += nb;
@@ -922,7 +938,7 @@ __device__ __forceinline__ void struct_body(FillLds &L, const SearchArgs &a, con
 }  // namespace
 
 __global__ __launch_bounds__(64) void k_struct_count(SearchArgs a) {
-    __shared__ FillLds L;
+    __shared__ StructLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     const SearchCloud C = group_cloud(a, g);
@@ -936,7 +952,7 @@ __global__ __launch_bounds__(64) void k_struct_count(SearchArgs a) {
 }
 
 __global__ __launch_bounds__(64) void k_struct_fill(SearchArgs a) {
-    __shared__ FillLds L;
+    __shared__ StructLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     // either buffer too small: write nothing
