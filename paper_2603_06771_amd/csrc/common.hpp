@@ -58,6 +58,18 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Orders the LDS accesses of a workgroup made of a single wave: LDS writes of
+// any lane before the call are seen by LDS reads of every lane after it.  A
+// wave's LDS instructions execute in issue order, so no wait instruction is
+// needed; the wavefront-scope fences keep the compiler from moving memory
+// accesses across the call.  Unlike a workgroup barrier, it does not wait for
+// the wave's outstanding global stores.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // number of set bits of m below this lane
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),

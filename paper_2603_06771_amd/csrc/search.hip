@@ -212,7 +212,7 @@ __device__ __forceinline__ int make_segments(Lds &L, const Query &q, float jump,
             L.seg[s][5] = b5;
         }
     }
-    __syncthreads();
+    wave_sync();
     if (sid_out) *sid_out = sid;
     return nseg;
 }
@@ -238,7 +238,7 @@ __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ no
     const int lane = lane_id();
     if (lane == 0) L.stack[0] = 0;
     int sp = 1, ncand = 0;
-    __syncthreads();
+    wave_sync();
     while (sp > 0) {
         int take = (kStack - sp) / 7;
         if (take > kWave) take = kWave;
@@ -246,7 +246,7 @@ __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ no
         if (take < 1) take = 1;
         const int node = lane < take ? L.stack[sp - take + lane] : -1;
         sp -= take;
-        __syncthreads();
+        wave_sync();
         sfc_node nd;
         int32_t ch = -1;
         bool keep = false;
@@ -277,7 +277,7 @@ __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ no
             if constexpr (std::is_same<Lds, WaveLds>::value) L.cnode[at] = nd;
         }
         ncand += __popcll(m_c);
-        __syncthreads();
+        wave_sync();
         if (ncand > kCand - kWave || (sp == 0 && ncand > 0)) {
             sweep(ncand);
             ncand = 0;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
     const uint32_t incl = wave_inclusive_sum(sz);
     L.cincl[lane] = incl;
     const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
-    __syncthreads();
+    wave_sync();
     uint32_t kept = 0;  // the same in every lane
     for (uint32_t base = 0; base < total; base += kWave) {
         const uint32_t p = base + lane;
@@ -337,9 +337,9 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
         }
         kept += static_cast<uint32_t>(__popcll(km));
         if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
-            __syncthreads();
+            wave_sync();
             body(kept);
-            __syncthreads();
+            wave_sync();
             kept = 0;
         }
     }
@@ -513,7 +513,7 @@ __device__ __forceinline__ uint32_t classify_segments(Lds &L, const sfc_node *__
     *mixed = mx;
     *touched = tc;
     *full = fm;
-    __syncthreads();
+    wave_sync();
     return len;
 }
 
@@ -532,7 +532,7 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
     const uint32_t incl = wave_inclusive_sum(((need >> lane) & 1ull) ? len : 0u);
     L.cincl[lane] = incl;
     const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
-    __syncthreads();
+    wave_sync();
     uint32_t kept = 0;  // points staged for the next round (the same in every lane)
     for (uint32_t base = 0; base < total; base += kWave) {
         const uint32_t p = base + lane;
@@ -563,9 +563,9 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
         }
         kept += static_cast<uint32_t>(__popcll(km));
         if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
-            __syncthreads();
+            wave_sync();
             body(kept);
-            __syncthreads();
+            wave_sync();
             kept = 0;
         }
     }
@@ -614,7 +614,7 @@ __device__ __forceinline__ void walk_one(Lds &L, const SearchCloud &C, float qx,
         L.seg[0][4] = qy;
         L.seg[0][5] = qz;
     }
-    __syncthreads();
+    wave_sync();
     auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, 1, nd, r, r2); };
     auto batches = [&](int ncand) {
         for (int c0 = 0; c0 < ncand; c0 += kWave) {
@@ -736,8 +736,13 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
     int sid = 0;
     const int nseg = make_segments(L, q, 2.0f * r, &sid);
     // an invalid lane owns an empty row and never appends
-    uint64_t gpos = q.valid ? a.offsets[row] : 0;
-    const uint64_t gend = q.valid ? a.offsets[row + 1] : 0;
+    // loaded by every lane (a lane without a query reads row 0 and drops it),
+    // so the wait for the loads is not left inside a branch
+    const int64_t orow = q.valid ? row : 0;
+    const uint64_t o0 = a.offsets[orow], o1 = a.offsets[orow + 1];
+    uint64_t gpos = q.valid ? o0 : 0ull;
+    const uint64_t gend = q.valid ? o1 : 0ull;
+    uint64_t left = gend > gpos ? gend - gpos : 0ull;  // entries the row can still take
     if (may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
         defer_group(a, lg + C.g0);
         return;
@@ -760,12 +765,11 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         if (!fm) return;
         const int nf = __popcll(fm);
         if (go) {
-            const uint64_t room = gend > gpos ? gend - gpos : 0ull;
             L.fpos[lane] = gpos;
-                L.flim[lane] = static_cast<uint8_t>(room < nb ? room : nb);
+            L.flim[lane] = static_cast<uint8_t>(left < nb ? left : nb);
             L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
         }
-        __syncthreads();
+        wave_sync();
         for (int i0 = 0; i0 < nf; i0 += 2) {
             const int i = i0 + half;
             if (i < nf) {
@@ -775,9 +779,10 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         }
         if (go) {
             gpos += nb;
+            left -= left < nb ? left : nb;
             nb = 0;
         }
-        __syncthreads();
+        wave_sync();
     };
     auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
     auto sweep = [&](int ncand) {
@@ -866,7 +871,7 @@ __device__ __forceinline__ void struct_body(StructLds &L, const SearchArgs &a, c
                 L.flim[lane] = static_cast<uint8_t>(room < nb ? room : nb);
                 L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
             }
-            __syncthreads();
+            wave_sync();
             for (int i = half; i < nf; i += 2) {
                 const int l = L.flist[i];
                 if (hl < L.flim[l])
@@ -876,7 +881,7 @@ __device__ __forceinline__ void struct_body(StructLds &L, const SearchArgs &a, c
                 gpos += nb;
                 nb = 0;
             }
-            __syncthreads();
+            wave_sync();
         };
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
@@ -1191,7 +1196,7 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
             const float m = wave_max_u(in ? bound : 0.0f);
             if (lane == 0) s_segr2[sg] = m < INFINITY ? nextafterf(m, INFINITY) : INFINITY;
         }
-        __syncthreads();
+        wave_sync();
         auto accept = [&](const sfc_node &nd) {
             bool hit = false;
             for (int sg = 0; sg < nseg; ++sg)
@@ -1309,7 +1314,7 @@ __device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds<BUF> &L, int &cnt, 
         else
             lo = mid + 1;
     }
-    __syncthreads();
+    wave_sync();
     int at = 0;
 #pragma unroll
     for (int i = 0; i < BUF / kWave; ++i) {
@@ -1318,7 +1323,7 @@ __device__ __forceinline__ int64_t keep_k_smallest(KnnOneLds<BUF> &L, int &cnt, 
         if (keep) L.buf[at + static_cast<int>(rank_below(m))] = v[i];
         at += __popcll(m);
     }
-    __syncthreads();
+    wave_sync();
     cnt = at;
     return lo;
 }
@@ -1350,7 +1355,7 @@ __device__ __forceinline__ void knn_one(KnnOneLds<BUF> &L, const SearchCloud &C,
                 if (h) L.buf[cnt + static_cast<int>(rank_below(m))] = pack(d, __float_as_uint(p.w));
                 cnt += __popcll(m);
             }
-            __syncthreads();
+            wave_sync();
         });
     // more keys than lanes (or than k) are cut back to the k best first
     if (cnt > (k < kWave ? kWave : k)) keep_k_smallest(L, cnt, k);
@@ -1369,7 +1374,7 @@ __device__ __forceinline__ void knn_one(KnnOneLds<BUF> &L, const SearchCloud &C,
         oi[i] = 0xFFFFFFFFu;
         od[i] = INFINITY;
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // tau for one query with the whole wave: the k-th smallest d2 over the
