@@ -66,6 +66,7 @@ constexpr int kStage = SFC_STAGE;     // points staged per round
 constexpr int kRowCap = SFC_ROWCAP;   // fill: staged output entries per query
 constexpr int kChunk = SFC_CHUNK;     // fill: points swept between flush checks
 constexpr int kSegMax = 8;            // query segments per wave
+constexpr float kJumpSteps = 5.0f;    // radius search: segment cut distance in mean curve steps (at least)
 static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0 && kStage >= 64 && kStage <= 256,
               "tile parameters");
 
@@ -173,15 +174,25 @@ struct WaveLds {
 // queries, cutting where two consecutive queries are more than `jump` apart
 // (the largest such steps first).  A space-filling curve visits empty space
 // between occupied regions, so consecutive points can be far apart; one box
-// over such a group would cover the whole gap.  Writes the run boxes to
-// L.seg and returns their number.
+// over such a group would cover the whole gap.  With step_factor > 0 the
+// cut distance grows towards step_factor times the group's mean step (the
+// point spacing along the curve), up to twice `jump`, so groups whose
+// radius is small next to the spacing are not cut into pieces whose extra
+// box tests cost more than the gaps save.  Writes the run boxes to L.seg
+// and returns their number.
 template <typename Lds>
-__device__ __forceinline__ int make_segments(Lds &L, const Query &q, float jump, int *sid_out) {
+__device__ __forceinline__ int make_segments(Lds &L, const Query &q, float jump, int *sid_out,
+                                             float step_factor = 0.0f) {
     const int lane = lane_id();
     const float px = __shfl_up(q.x, 1), py = __shfl_up(q.y, 1), pz = __shfl_up(q.z, 1);
     const int pv = __shfl_up(q.valid ? 1 : 0, 1);
     float step = 0.0f;
-    if (lane > 0 && q.valid && pv) step = fmaxf(fabsf(q.x - px), fmaxf(fabsf(q.y - py), fabsf(q.z - pz)));
+    const bool has = lane > 0 && q.valid && pv;
+    if (has) step = fmaxf(fabsf(q.x - px), fmaxf(fabsf(q.y - py), fabsf(q.z - pz)));
+    if (step_factor > 0.0f) {
+        const int ns = __popcll(ballot(has));
+        if (ns > 0) jump = fmaxf(jump, fminf(2.0f * jump, step_factor * wave_sum_f(step) / static_cast<float>(ns)));
+    }
     const bool brk = step > jump;
     uint64_t bm = ballot(brk);
     if (__popcll(bm) > kSegMax - 1) {
@@ -656,7 +667,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
     const bool prune = !(a.flags & SFC_NO_PRUNE);
     uint32_t cnt = 0;
     int sid = 0;
-    const int nseg = r > 0.0f ? make_segments(L, q, 2.0f * r, &sid) : 0;
+    const int nseg = r > 0.0f ? make_segments(L, q, 2.0f * r, &sid, kJumpSteps) : 0;
     if (r > 0.0f && may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
         defer_group(a, lg + C.g0);
         return;
@@ -734,7 +745,7 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
     if (!(r > 0.0f)) return;  // empty rows
     const bool prune = !(a.flags & SFC_NO_PRUNE);
     int sid = 0;
-    const int nseg = make_segments(L, q, 2.0f * r, &sid);
+    const int nseg = make_segments(L, q, 2.0f * r, &sid, kJumpSteps);
     // an invalid lane owns an empty row and never appends
     // loaded by every lane (a lane without a query reads row 0 and drops it),
     // so the wait for the loads is not left inside a branch
@@ -849,7 +860,7 @@ __device__ __forceinline__ void struct_body(StructLds &L, const SearchArgs &a, c
     uint32_t nr = 0, np = 0;
     if (r > 0.0f) {
         int sid = 0;
-        const int nseg = make_segments(L, q, 2.0f * r, &sid);
+        const int nseg = make_segments(L, q, 2.0f * r, &sid, kJumpSteps);
         uint64_t rpos = 0, rend = 0, gpos = 0, gend = 0;
         if (fill && q.valid) {
             rpos = a.roffsets[row];
@@ -1650,23 +1661,31 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
     a.nspread = w.nspread;
     if (!(a.flags & SFC_REUSE_COUNTS)) {
         if (groups > 0) {
-            k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
-            SFC_LAUNCH_CHECK("k_reset_spread");
+            if (a.queries) {
+                k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
+                SFC_LAUNCH_CHECK("k_reset_spread");
+            }
             k_radius_count<<<grid, 64, 0, s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_count");
-            k_radius_count_spread<<<sgrid, 64, 0, s>>>(a);
-            SFC_LAUNCH_CHECK("k_radius_count_spread");
+            if (a.queries) {  // only external queries are ever deferred
+                k_radius_count_spread<<<sgrid, 64, 0, s>>>(a);
+                SFC_LAUNCH_CHECK("k_radius_count_spread");
+            }
         }
         const int rc = scan_u32_to_u64(counts, a.nq_total, const_cast<uint64_t *>(a.offsets), true, scan_ws, s);
         if (rc) return rc;
     }
     if (a.indices && groups > 0) {
-        k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
-        SFC_LAUNCH_CHECK("k_reset_spread");
+        if (a.queries) {
+            k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
+            SFC_LAUNCH_CHECK("k_reset_spread");
+        }
         k_radius_fill<<<grid, 64, 0, s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");
-        k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
-        SFC_LAUNCH_CHECK("k_radius_fill_spread");
+        if (a.queries) {
+            k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_fill_spread");
+        }
     }
     return SFC_OK;
 }
@@ -1709,8 +1728,10 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
     else
         k_knn<32><<<grid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn");
-    k_knn_spread<<<qgrid, 64, 0, s>>>(a);
-    SFC_LAUNCH_CHECK("k_knn_spread");
+    if (a.queries) {  // only external queries are ever deferred
+        k_knn_spread<<<qgrid, 64, 0, s>>>(a);
+        SFC_LAUNCH_CHECK("k_knn_spread");
+    }
     return SFC_OK;
 }
 
