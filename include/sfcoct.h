@@ -42,7 +42,7 @@ typedef enum {
     SFC_EWORKSPACE = -2,  /* workspace too small or misaligned */
     SFC_ECAPACITY = -3,   /* reserved: output capacity checks are device-side */
     SFC_EHIP = -4,        /* a HIP runtime call or kernel launch failed */
-    SFC_ENOTSUP = -5      /* valid but unsupported request (e.g. k > 32) */
+    SFC_ENOTSUP = -5      /* valid but unsupported request (e.g. k > 512) */
 } sfc_status;
 
 /* Space-filling curves of Section 4 (4.1 Morton, 4.2 Hilbert). */
@@ -195,7 +195,7 @@ int radius_search_struct(const sfc_octree *tree, const float *queries, int64_t n
  *            external queries are reordered along the curve inside the call
  *            (as radius_search without SFC_QUERIES_ORDERED)
  *   idx      [nq*k] output indices;  d2 [nq*k] output squared distances
- * 1 <= k <= 512 (SFC_ENOTSUP above).  k <= 32 keeps each query's list in
+ * 1 <= k <= 512 (SFC_ENOTSUP above).  k <= 64 keeps each query's list in
  * registers (64 queries per wave); larger k takes one query per wave with a
  * candidate buffer in LDS. */
 int knn_search(const sfc_octree *tree, const float *queries, int64_t nq, int k, uint32_t *idx,
@@ -219,7 +219,7 @@ typedef struct sfc_cloud {
     uint32_t leaf_size;  /* N_max, >= 1 */
     int32_t kernel;      /* radius search: sfc_kernel */
     float r;             /* radius search: radius (r <= 0: empty rows) */
-    int32_t k;           /* k-NN: 1..32 */
+    int32_t k;           /* k-NN: 1..kstride (at most 512) */
     int64_t q_offset;    /* search: first row of the cloud in the concatenated queries */
     int64_t nq;          /* search: queries of the cloud (cloud queries: nq == n) */
     sfc_octree tree;     /* filled by octree_batch_layout */

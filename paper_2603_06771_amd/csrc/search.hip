@@ -1293,7 +1293,8 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
 // ---------------------------------------------------- k-NN of spread groups
 namespace {
 
-constexpr int kKnnBuf = 256;        // candidate keys held per query (k <= 32)
+constexpr int kKnnRegK = 64;        // largest k of the register (group) kernel
+constexpr int kKnnBuf = 256;        // candidate keys held per query (k <= kKnnRegK)
 constexpr int kKnnBufLarge = 1024;  // the same for k up to kKnnMaxK
 constexpr int kKnnMaxK = 512;
 
@@ -1438,7 +1439,7 @@ __global__ __launch_bounds__(64) void k_knn_spread(SearchArgs a) {
         if (lr >= C.nq) continue;
         int64_t row;
         const Query q = lane_query(a, C, lr, &row);
-        const float tau = window_tau<1>(a, C, q, lr, C.k);
+        const float tau = window_tau<2 * kKnnRegK / kWave>(a, C, q, lr, C.k);
         knn_one(L, C, q, C.k, tau, a.idx + row * a.kstride, a.d2 + row * a.kstride, a.kstride);
     }
 }
@@ -1712,7 +1713,7 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
     }
     const unsigned grid = static_cast<unsigned>(xcd_grid(groups));
     const unsigned qgrid = static_cast<unsigned>(xcd_grid(std::min<int64_t>(groups * kWave, 1 << 16)));
-    if (kmax > 32) {
+    if (kmax > kKnnRegK) {
         k_knn_large<<<qgrid, 64, 0, s>>>(a);
         SFC_LAUNCH_CHECK("k_knn_large");
         return SFC_OK;
@@ -1725,8 +1726,10 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
         k_knn<8><<<grid, 64, 0, s>>>(a);
     else if (kmax <= 16)
         k_knn<16><<<grid, 64, 0, s>>>(a);
-    else
+    else if (kmax <= 32)
         k_knn<32><<<grid, 64, 0, s>>>(a);
+    else
+        k_knn<64><<<grid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn");
     if (a.queries) {  // only external queries are ever deferred
         k_knn_spread<<<qgrid, 64, 0, s>>>(a);

@@ -154,10 +154,12 @@ def test_batch_radius_capacity(sfc):
 
 
 KS = [8, 3, 1, 32, 16, 4, 12, 24]
+KS64 = [8, 3, 1, 48, 16, 64, 12, 40]  # largest k of the register kernel
 
 
+@pytest.mark.parametrize("ks,kstride", [(KS, 32), (KS64, 64)])
 @pytest.mark.parametrize("external", [False, True])
-def test_batch_knn(sfc, external):
+def test_batch_knn(sfc, external, ks, kstride):
     import torch
     batch, clouds = _mixed_batch(sfc)
     rng = np.random.default_rng(9)
@@ -170,8 +172,8 @@ def test_batch_knn(sfc, external):
         q_sizes = [x.shape[0] for x in qs]
     else:
         qs, q, q_sizes = None, None, None
-    announce(f"batch knn mixed k, external={external}")
-    idx, d2 = sfc.knn_search_batched(batch, q, q_sizes, KS, kstride=32)
+    announce(f"batch knn mixed k (max {max(ks)}), external={external}")
+    idx, d2 = sfc.knn_search_batched(batch, q, q_sizes, ks, kstride=kstride)
     torch.cuda.synchronize()
     gi = idx.cpu().numpy().view(np.uint32)
     gd = d2.cpu().numpy()
@@ -182,7 +184,7 @@ def test_batch_knn(sfc, external):
         else:
             perm = batch.tree(cl).perm().cpu().numpy().view(np.uint32)
             qp = pts[perm]
-        k = KS[cl]
+        k = ks[cl]
         ridx, rd2 = oracle.knn(pts, qp, k)
         rows = slice(q0, q0 + qp.shape[0])
         assert np.array_equal(gi[rows, :k], ridx), f"cloud {cl} k={k}: indices differ"

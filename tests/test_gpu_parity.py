@@ -217,7 +217,7 @@ def _knn_case(sfc, pts, curve, leaf, k, queries=None):
                           f"oracle {ridx[bad[0]]} {rd2[bad[0]]}"
 
 
-@pytest.mark.parametrize("k", [1, 5, 8, 16, 32])
+@pytest.mark.parametrize("k", [1, 5, 8, 16, 32, 33, 64])
 @pytest.mark.parametrize("curve", CURVES)
 def test_knn_lidar(sfc, k, curve):
     pts = _cloud("lidar", 40001, seed=12)
@@ -225,7 +225,7 @@ def test_knn_lidar(sfc, k, curve):
     _knn_case(sfc, pts, curve, 32, k)
 
 
-@pytest.mark.parametrize("k", [1, 8, 32])
+@pytest.mark.parametrize("k", [1, 8, 32, 64])
 def test_knn_sparse_queries(sfc, k):
     # queries far apart: waves take them one at a time
     rng = np.random.default_rng(23)
@@ -241,7 +241,7 @@ def test_knn_sparse_queries(sfc, k):
     _knn_case(sfc, dup, "morton", 8, k, queries=dup[np.sort(rng.choice(dup.shape[0], 500, replace=False))])
 
 
-@pytest.mark.parametrize("k", [33, 64, 100, 300, 512])
+@pytest.mark.parametrize("k", [65, 100, 300, 512])
 def test_knn_large_k(sfc, k):
     # k above the register lists: one query per wave, LDS candidate buffer
     pts = _cloud("lidar", 20000, seed=26)
@@ -262,7 +262,7 @@ def test_knn_large_k_small_cloud_and_ties(sfc):
 
 def test_knn_duplicates_ties(sfc):
     pts = _cloud("dup", 20000, seed=13)
-    for k in (4, 16, 32):
+    for k in (4, 16, 32, 64):
         announce(f"knn dup k={k}")
         _knn_case(sfc, pts, "hilbert", 8, k)
 
