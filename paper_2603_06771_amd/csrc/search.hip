@@ -1728,6 +1728,8 @@ int knn_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t group
         k_knn<16><<<grid, 64, 0, s>>>(a);
     else if (kmax <= 32)
         k_knn<32><<<grid, 64, 0, s>>>(a);
+    else if (kmax <= 48)
+        k_knn<48><<<grid, 64, 0, s>>>(a);
     else
         k_knn<64><<<grid, 64, 0, s>>>(a);
     SFC_LAUNCH_CHECK("k_knn");

@@ -217,7 +217,7 @@ def _knn_case(sfc, pts, curve, leaf, k, queries=None):
                           f"oracle {ridx[bad[0]]} {rd2[bad[0]]}"
 
 
-@pytest.mark.parametrize("k", [1, 5, 8, 16, 32, 33, 64])
+@pytest.mark.parametrize("k", [1, 5, 8, 16, 32, 33, 48, 64])
 @pytest.mark.parametrize("curve", CURVES)
 def test_knn_lidar(sfc, k, curve):
     pts = _cloud("lidar", 40001, seed=12)
