@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -116,7 +117,7 @@ def bench_batched(args):
     log(f"[bench] generated {len(sizes)} clouds, {n} points in {time.perf_counter() - t0:.1f} s")
 
     tune = autotune.tune_leaf(xyz, sizes, kernels, radii, "hilbert", repeats=args.tune_repeats,
-                              cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"), log=log)
+                              cache_path=os.path.join(tempfile.gettempdir(), "sfcoct_bench_autotune.json"), log=log)
     leaves = tune["leaf"]
 
     plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii)
@@ -374,8 +375,8 @@ def bench_subset(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split is "
-              f"described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the search is built for one "
+              f"GPU's share of the data; sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
