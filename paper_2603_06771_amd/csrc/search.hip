@@ -241,13 +241,15 @@ struct HasEnds : std::false_type {};
 template <typename T>
 struct HasEnds<T, std::void_t<decltype(std::declval<T &>().cend)>> : std::true_type {};
 
-// Walks the tree; each time the candidate list fills up (or the walk ends)
-// calls sweep(ncand).  accept(node) decides whether the wave keeps a node.
+// Walks the tree below node `start` (the root by default); each time the
+// candidate list fills up (or the walk ends) calls sweep(ncand).
+// accept(node) decides whether the wave keeps a node.
 template <typename Lds, typename Accept, typename Sweep>
 __device__ __forceinline__ void traverse(Lds &L, const sfc_node *__restrict__ nodes,
-                                         const int32_t *__restrict__ child, Accept accept, Sweep sweep) {
+                                         const int32_t *__restrict__ child, Accept accept, Sweep sweep,
+                                         int start = 0) {
     const int lane = lane_id();
-    if (lane == 0) L.stack[0] = 0;
+    if (lane == 0) L.stack[0] = start;
     int sp = 1, ncand = 0;
     wave_sync();
     while (sp > 0) {
@@ -657,6 +659,62 @@ __device__ __forceinline__ uint32_t count_one(RadLds &L, const SearchCloud &C, f
     return cnt;
 }
 
+// The deepest node whose cell holds every point that may be a neighbour of
+// the wave's queries, so the walk can start there instead of at the root.
+// The reach is the union of the segment boxes grown by r (and widened by a
+// few ulps of the coordinates against rounding); for the 2D kernels its z
+// range is the cloud's whole extent.  The cell discretisation of the codes
+// is monotone, so every such point lies in the cells between those of the
+// reach's corners, i.e. inside the deepest cell that holds both; the walk
+// down to it follows the digits of any code inside it (a query's own code:
+// the queries lie in the reach, also in z for the 2D kernels, whose z range
+// takes in the queries' too), internal nodes having all 8 children in digit
+// order.
+template <int KERNEL, typename Lds>
+__device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, const SearchCloud &C, int nseg, float r,
+                                          const Query &q, int64_t lr) {
+    if (C.n <= 0 || a.queries) return 0;  // external queries: no code at hand, start at the root
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int s = 0; s < nseg; ++s) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fminf(lo[d], L.seg[s][d]);
+            hi[d] = fmaxf(hi[d], L.seg[s][3 + d]);
+        }
+    }
+    const sfc_frame f = *C.frame;
+    const uint32_t ncell = 1u << f.bits;
+    int span = 0;  // bits in which the corner cells differ, over the axes
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float rl = lo[d], rh = hi[d], g = r;
+        if ((KERNEL == SFC_CIRCLE || KERNEL == SFC_SQUARE) && d == 2) {
+            rl = fminf(rl, C.nodes[0].lo[2]);
+            rh = fmaxf(rh, C.nodes[0].hi[2]);
+            g = 0.0f;
+        }
+        const float e = (fabsf(rl) + fabsf(rh) + g) * 1e-6f;
+        const uint32_t c0 = cell_of(rl - g - e, f.lo[d], f.scale, ncell);
+        const uint32_t c1 = cell_of(rh + g + e, f.lo[d], f.scale, ncell);
+        const uint32_t x = c0 ^ c1;
+        const int b = x ? 32 - __clz(static_cast<int>(x)) : 0;
+        span = b > span ? b : span;
+    }
+    const int l = f.bits - span;  // level of the cell holding the reach
+    if (l <= 0 || !(lo[0] <= hi[0])) return 0;
+    // a code inside that cell: the first valid lane's query
+    const int first = __ffsll(static_cast<long long>(ballot(q.valid))) - 1;
+    if (first < 0) return 0;
+    const uint64_t key = readlane_u64(C.keys[lr < C.n ? lr : 0], first);
+    int node = 0;
+    for (int d = 1; d <= l; ++d) {
+        const int c = C.child[node];
+        if (c < 0) break;
+        node = c + static_cast<int>((key >> (3 * (f.bits - d))) & 7u);
+    }
+    return node;
+}
+
 template <int KERNEL>
 __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
@@ -697,7 +755,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 });
             }
         };
-        traverse(L, C.nodes, C.child, accept, sweep);
+        traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
     }
     if (q.valid) a.counts[row] = cnt;
 }
@@ -836,7 +894,7 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
             });
         }
     };
-    traverse(L, C.nodes, C.child, accept, sweep);
+    traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
     flush(0);
 }
 
