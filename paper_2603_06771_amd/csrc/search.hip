@@ -538,15 +538,21 @@ __device__ __forceinline__ uint32_t classify_segments(Lds &L, const sfc_node *__
 // the conservative gap test of the segment boxes, exact by the monotonicity
 // argument): a point outside every grown segment box is a neighbour of none
 // of the wave's queries, so only the sweep's work changes, never a result.
+//
+// With `carry`, the staged points stay for the next batch: body runs only
+// when the buffer is full, *carry holds the count in and out, and the caller
+// sweeps what is left after its last batch (bodies that do not depend on the
+// batch; fuller rounds mean fewer round ends).
 template <int KERNEL, bool OWNER = false, typename Lds, typename Body>
 __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ pts, int c0, int m, uint64_t need,
-                                            uint32_t len, int nseg, float r, float r2, Body body) {
+                                            uint32_t len, int nseg, float r, float r2, Body body,
+                                            uint32_t *carry = nullptr) {
     const int lane = lane_id();
     const uint32_t incl = wave_inclusive_sum(((need >> lane) & 1ull) ? len : 0u);
     L.cincl[lane] = incl;
     const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
     wave_sync();
-    uint32_t kept = 0;  // points staged for the next round (the same in every lane)
+    uint32_t kept = carry ? *carry : 0u;  // points staged for the next round (the same in every lane)
     for (uint32_t base = 0; base < total; base += kWave) {
         const uint32_t p = base + lane;
         bool keep = false;
@@ -575,13 +581,14 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
             if constexpr (OWNER) L.owner[kept + rank_below(km)] = static_cast<uint8_t>(lo);
         }
         kept += static_cast<uint32_t>(__popcll(km));
-        if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
+        if (kept > static_cast<uint32_t>(kStage - kWave) || (!carry && base + kWave >= total && kept > 0)) {
             wave_sync();
             body(kept);
             wave_sync();
             kept = 0;
         }
     }
+    if (carry) *carry = kept;
 }
 
 // A wave's queries are "spread" when the region every lane sweeps in the
@@ -731,6 +738,20 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
         return;
     }
     if (r > 0.0f) {
+        // every lane tests its query against the staged points
+        auto body = [&](uint32_t n_) {
+            const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
+            uint32_t t = 0;
+            for (; t + 4 <= n; t += 4) {
+                const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
+                cnt += point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                cnt += point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                cnt += point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+                cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
+            }
+            for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
+        };
+        uint32_t staged = 0;  // points staged and not yet swept, across candidate batches
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
             for (int c0 = 0; c0 < ncand; c0 += kWave) {
@@ -741,21 +762,14 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 // contained for my segment and not swept: count the whole node
                 for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
                 if (!mixed) continue;
-                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, [&](uint32_t n_) {
-                    const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
-                    uint32_t t = 0;
-                    for (; t + 4 <= n; t += 4) {
-                        const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
-                        cnt += point_hit<KERNEL>(p0, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                        cnt += point_hit<KERNEL>(p1, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                        cnt += point_hit<KERNEL>(p2, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                        cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                    }
-                    for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
-                });
+                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, body, &staged);
             }
         };
         traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
+        if (staged) {
+            wave_sync();
+            body(staged);
+        }
     }
     if (q.valid) a.counts[row] = cnt;
 }
@@ -853,6 +867,41 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         }
         wave_sync();
     };
+    // every lane tests its query against the staged points and appends the
+    // slots of its hits to its row
+    auto body = [&](uint32_t n_) {
+        const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
+        for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
+            flush(kRowCap - kChunk);
+            const uint32_t te = min(n, t0 + kChunk);
+            uint32_t t = t0;
+            uint8_t *w = myrow + nb;  // next free slot
+            for (; t + 4 <= te; t += 4) {
+                const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
+                const bool h0 = point_hit<KERNEL>(p0, qx, qy, qz, r, r2);
+                const bool h1 = point_hit<KERNEL>(p1, qx, qy, qz, r, r2);
+                const bool h2 = point_hit<KERNEL>(p2, qx, qy, qz, r, r2);
+                const bool h3 = point_hit<KERNEL>(p3, qx, qy, qz, r, r2);
+                // each slot is overwritten unless it holds a hit
+                *w = static_cast<uint8_t>(t + 0);
+                w += h0;
+                *w = static_cast<uint8_t>(t + 1);
+                w += h1;
+                *w = static_cast<uint8_t>(t + 2);
+                w += h2;
+                *w = static_cast<uint8_t>(t + 3);
+                w += h3;
+            }
+            for (; t < te; ++t) {
+                const bool h = point_hit<KERNEL>(L.pts[t], qx, qy, qz, r, r2);
+                *w = static_cast<uint8_t>(t);
+                w += h;
+            }
+            nb = static_cast<uint32_t>(w - myrow);
+        }
+        flush(0);  // the rows point into this round's staged points
+    };
+    uint32_t staged = 0;  // points staged and not yet swept, across candidate batches
     auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
     auto sweep = [&](int ncand) {
         for (int c0 = 0; c0 < ncand; c0 += kWave) {
@@ -860,41 +909,14 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
             uint64_t mixed, touched, full;
             const uint32_t len = classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
             if (!touched) continue;
-            stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, [&](uint32_t n_) {
-                const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
-                for (uint32_t t0 = 0; t0 < n; t0 += kChunk) {
-                    flush(kRowCap - kChunk);
-                    const uint32_t te = min(n, t0 + kChunk);
-                    uint32_t t = t0;
-                    uint8_t *w = myrow + nb;  // next free slot
-                    for (; t + 4 <= te; t += 4) {
-                        const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
-                        const bool h0 = point_hit<KERNEL>(p0, qx, qy, qz, r, r2);
-                        const bool h1 = point_hit<KERNEL>(p1, qx, qy, qz, r, r2);
-                        const bool h2 = point_hit<KERNEL>(p2, qx, qy, qz, r, r2);
-                        const bool h3 = point_hit<KERNEL>(p3, qx, qy, qz, r, r2);
-                        // each slot is overwritten unless it holds a hit
-                        *w = static_cast<uint8_t>(t + 0);
-                        w += h0;
-                        *w = static_cast<uint8_t>(t + 1);
-                        w += h1;
-                        *w = static_cast<uint8_t>(t + 2);
-                        w += h2;
-                        *w = static_cast<uint8_t>(t + 3);
-                        w += h3;
-                    }
-                    for (; t < te; ++t) {
-                        const bool h = point_hit<KERNEL>(L.pts[t], qx, qy, qz, r, r2);
-                        *w = static_cast<uint8_t>(t);
-                        w += h;
-                    }
-                    nb = static_cast<uint32_t>(w - myrow);
-                }
-                flush(0);  // the rows point into this round's staged points
-            });
+            stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, body, &staged);
         }
     };
     traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
+    if (staged) {
+        wave_sync();
+        body(staged);
+    }
     flush(0);
 }
 
