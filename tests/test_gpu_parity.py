@@ -163,6 +163,21 @@ def test_radius_sparse_queries(sfc, kernel):
         _radius_case(sfc, pts, "morton", 32, kernel, r, queries=q, prune=False)
 
 
+@pytest.mark.parametrize("curve", CURVES)
+def test_radius_georeferenced(sfc, curve):
+    # a tile at map coordinates: fp32 spacing 0.03 m in x and 0.5 m in y, so
+    # the arithmetic rounds coarsely and many points coincide (the walk's
+    # start node and every exactness argument must still hold)
+    pts = _cloud("lidar", 30000, seed=31)
+    geo = (pts.astype(np.float64) + np.array([512345.5, 4312345.25, 120.0])).astype(np.float32)
+    for kernel in KERNELS:
+        for r in (0.5, 2.0):
+            announce(f"radius georeferenced {curve} {kernel} r={r}")
+            _radius_case(sfc, geo, curve, 32, kernel, r)
+    announce(f"knn georeferenced {curve}")
+    _knn_case(sfc, geo, curve, 32, 16)
+
+
 def test_radius_no_prune_flag(sfc):
     pts = _cloud("lidar", 30000, seed=9)
     announce("radius no-prune")
