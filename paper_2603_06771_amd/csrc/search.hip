@@ -1345,7 +1345,16 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
                 });
             }
         };
-        traverse(L, C.nodes, C.child, accept, sweep);
+        // short lists start below the root (the reach: the segment boxes grown
+        // by the largest segment bound); for long lists the extra registers
+        // cost more occupancy than the skipped levels save
+        int start = 0;
+        if constexpr (KMAX <= 16) {
+            float smax = 0.0f;
+            for (int sg = 0; sg < nseg; ++sg) smax = fmaxf(smax, s_segr2[sg]);
+            if (smax < INFINITY) start = start_node<SFC_SPHERE>(L, a, C, nseg, sqrtf(smax), qa, lr);
+        }
+        traverse(L, C.nodes, C.child, accept, sweep, start);
         // done: the answer lies within the radius already searched
         const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
         if (round == 0) active = active && !(tau <= R1 || kth <= R1);
