@@ -2,20 +2,24 @@
 // (neighboursPrune), and Section 3.3 k-nearest-neighbour search, on the
 // linear octree.
 //
-// GPU mapping (one wave = one workgroup):
+// GPU mapping (one wave = one workgroup, so LDS is ordered with
+// wavefront-scope fences, never a workgroup barrier):
 //  * A group is 64 consecutive queries; for cloud queries these are 64
 //    consecutive points of the curve, so their union is compact.  Lane i owns
-//    query i of the group.
-//  * Traversal: the wave walks the tree from the root with an LDS stack, 64
-//    nodes per step (one per lane).  A node is kept when it may hold a
-//    neighbour of SOME query of the group (its box against the group's box
+//    query i of the group.  The group is cut into segments where consecutive
+//    queries jump apart; the segment boxes drive every shortcut below.
+//  * Traversal: the wave walks the tree with an LDS stack, 64 nodes per step
+//    (one per lane), from the root or, for cloud queries, from the deepest
+//    node whose cell holds the group's whole reach.  A node is kept when it
+//    may hold a neighbour of SOME query (its box against the segment boxes
 //    with the kernel's norm); kept leaves become candidates.
-//  * Sweep: the candidates' points are staged in LDS (coalesced loads), then
-//    every candidate is classified per query against the node's tight box:
-//    disjoint (skip), contained (all its points are neighbours: Section 5.1
-//    step 1a) or partial (test point by point: step 2).  The point loop reads
-//    LDS with a wave-uniform address (broadcast) and each lane tests its own
-//    query.
+//  * Sweep: candidates are classified (lane = candidate) against each
+//    segment box: disjoint (skip), contained for every query of the segment
+//    (counted without touching the points: Section 5.1 step 1a) or partial.
+//    Points of partial candidates are staged in LDS (coalesced loads, points
+//    no segment can reach dropped, carried over between candidate batches),
+//    then every lane tests its own query against every staged point with a
+//    wave-uniform LDS address (broadcast; step 2).
 //  * Exactness: boxes are the tight fp32 boxes of the node's points.  fp32
 //    subtraction, product and sum are monotone, so a box corner bounds every
 //    point's fp32 expression from the same side; the shortcuts therefore give
@@ -25,9 +29,10 @@
 //    to its own LDS row (one byte each), and rows are flushed to HBM with
 //    coalesced half-wave stores when they fill up and at the end of every
 //    staging round.
-//  * k-NN: lane-owned top-k of (d2, index) keys in registers (descending,
-//    so the current k-th is always register 0), seeded with an upper bound
-//    of the k-th distance taken from the query's k curve neighbours.
+//  * k-NN: lane-owned top-k (k <= 64) of (d2, index) keys in registers
+//    (descending, so the current k-th is always register 0), seeded with an
+//    upper bound of the k-th distance taken from the query's curve
+//    neighbours; larger k takes one query per wave with an LDS buffer.
 // Roofline: the fill pass is bound by HBM writes of the indices for large
 // neighbourhoods and by VALU (candidate tests) for small ones.
 #include <algorithm>

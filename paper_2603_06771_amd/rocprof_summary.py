@@ -129,8 +129,15 @@ def traffic(fetch_path: str, write_path: str, kernel: str = "k_radius_fill", min
 
 
 def source_sha(path: str) -> str:
+    """Hash of a source file's code: comments and whitespace left out, so a
+    record stays valid across comment edits and is void once the code
+    changes."""
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
 
 
 def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, min_kib: float = 1024.0) -> dict:
