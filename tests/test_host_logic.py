@@ -90,3 +90,17 @@ def test_served_and_batch_generators():
         if c["kind"] == "uniform":
             side = n ** (1.0 / 3.0)
             assert c["points"].min() >= 0.0 and c["points"].max() <= side
+
+
+def test_source_sha_ignores_comments_only(tmp_path):
+    """The traffic record is tied to the kernel code: comment and whitespace
+    edits keep its hash, a code change voids it."""
+    from paper_2603_06771_amd.rocprof_summary import source_sha
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("// header\nint f(int x) {\n    return x + 1;  // one\n}\n/* block\n comment */\n")
+    b.write_text("// another header\n\nint f(int x) {\n  return x + 1;\n}\n")
+    c.write_text("// header\nint f(int x) {\n    return x + 2;  // one\n}\n")
+    assert source_sha(str(a)) == source_sha(str(b))
+    assert source_sha(str(a)) != source_sha(str(c))
