@@ -178,6 +178,22 @@ def test_radius_georeferenced(sfc, curve):
     _knn_case(sfc, geo, curve, 32, 16)
 
 
+def test_radius_degenerate_clouds(sfc):
+    # every point the same (zero extent), points on a line (zero extent in y
+    # and z), a single point: frames, cells, start nodes and ties
+    rng = np.random.default_rng(33)
+    same = np.tile(np.array([[3.25, -1.5, 7.0]], np.float32), (3000, 1))
+    line = np.zeros((4000, 3), np.float32)
+    line[:, 0] = np.sort(rng.uniform(0.0, 40.0, 4000)).astype(np.float32)
+    one = np.array([[0.5, 0.5, 0.5]], np.float32)
+    for name, pts in (("same", same), ("line", line), ("one", one)):
+        for kernel in KERNELS:
+            announce(f"radius degenerate {name} {kernel}")
+            _radius_case(sfc, pts, "hilbert", 16, kernel, 0.3)
+        announce(f"knn degenerate {name}")
+        _knn_case(sfc, pts, "morton", 16, 8)
+
+
 def test_radius_no_prune_flag(sfc):
     pts = _cloud("lidar", 30000, seed=9)
     announce("radius no-prune")
