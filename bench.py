@@ -538,6 +538,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": tot_bytes / len(combos)},
         "build_ms": {c: round(v, 3) for c, v in build_ms.items()},
+        # beside the end-to-end value: the searches alone (the step less its
+        # event-timed builds) and the build throughput
+        "search_only": {"queries_per_s": queries_per_step / ((ms_per_step - sum(build_ms.values())) / 1e3),
+                        "ms_per_step": ms_per_step - sum(build_ms.values())},
+        "build_points_per_s": {c: n / (v / 1e3) for c, v in build_ms.items()},
         "tree": {c: {"n_nodes": infos[c]["n_nodes"], "n_leaves": infos[c]["n_leaves"], "depth": infos[c]["depth"]}
                  for c in CURVES},
         "detail": detail,

@@ -4,6 +4,7 @@
     python -m paper_2603_06771_amd.rocprof_summary trace <kernel_trace.csv> <kernel-name> [min_us]
     python -m paper_2603_06771_amd.rocprof_summary sq <counter_collection.csv> <kernel-name>
     python -m paper_2603_06771_amd.rocprof_summary l2 <counter_collection.csv> <kernel-name>
+    python -m paper_2603_06771_amd.rocprof_summary lds <counter_collection.csv> <kernel-name>
     python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> [kernel-substring]
 
@@ -92,6 +93,29 @@ def l2(path: str, kernel: str) -> str:
     return "\n".join(out)
 
 
+def lds(path: str, kernel: str) -> str:
+    """Per-dispatch LDS behaviour and occupancy of `kernel`: LDS instructions
+    and address-conflict cycles per wave, bank conflicts per LDS access
+    (derived counter LdsBankConflict) and the mean resident waves per CU
+    (MeanOccupancyPerCU)."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Kernel_Name"].split("(")[0].split("::")[-1] != kernel:
+            continue
+        d = per.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"].replace("_sum", "")] = float(r["Counter_Value"])
+        d["dur_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    out = [f"{'dispatch':>8s} {'dur_us':>9s} {'waves':>8s} {'LDS/w':>7s} {'addr/w':>8s} {'bank/access':>12s} "
+           f"{'waves/CU':>9s}"]
+    for dsp in sorted(per):
+        d = per[dsp]
+        w = max(d.get("SQ_WAVES", 1.0), 1.0)
+        out.append(f"{dsp:8d} {d['dur_us']:9.0f} {w:8.0f} {d.get('SQ_INSTS_LDS', float('nan')) / w:7.0f} "
+                   f"{d.get('SQ_LDS_ADDR_CONFLICT', float('nan')) / w:8.1f} {d.get('LdsBankConflict', float('nan')):12.4f} "
+                   f"{d.get('MeanOccupancyPerCU', float('nan')):9.1f}")
+    return "\n".join(out)
+
+
 def _per_dispatch(path: str, counter: str):
     rows = []
     for r in csv.DictReader(open(path)):
@@ -165,6 +189,8 @@ if __name__ == "__main__":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "l2":
         print(l2(sys.argv[2], sys.argv[3]))
+    elif sys.argv[1] == "lds":
+        print(lds(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "sq":
         print(sq(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "trace":
