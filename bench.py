@@ -5,16 +5,19 @@ One step is one pass of the whole hot path over the workload:
   for each curve in (Morton, Hilbert):
       encode -> radix sort -> reorder -> linear octree build
       for each kernel in (sphere, cube), r in (0.5, 1, 2, 3) m:
-          radius_search over every cloud point (count pass, scan, fill pass)
+          radius_search over every cloud point (count pass recording each
+          group's hits, scan, fill stage writing the rows from the records)
 so a step answers 16 x 10M radius queries.  Inputs are resident in HBM before
 the timed region; the output buffer is sized once (capacity protocol), so no
-host synchronisation happens inside a step.
+host synchronisation happens inside a step.  --no-record times the search
+fill instead (the same result).
 
-Prints ONE JSON line (see the keys below).  The fill kernel's achieved
+Prints ONE JSON line (see the keys below).  The fill stage's achieved
 bandwidth is measured with events on the launch stream around every fill
-launch; algorithmic bytes per fill launch are
-  16 B x queries (points read once) + 8 B x (queries + 1) (row offsets)
-  + 4 B x neighbours (indices written) + 36 B x nodes (tree read once).
+stage; its algorithmic bytes are
+  8 B x (queries + 1) (row offsets read) + 4 B x neighbours (indices written)
+and, for the search fill, also 16 B x queries (points read once) + 36 B x
+nodes (tree read once).
 The CPU baseline is the oracle (uniform-grid search) on a bounded sample.
 """
 from __future__ import annotations
@@ -31,6 +34,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the fill stage of a recorded-hits search: the two record-writing forms and
+# the search fill for groups whose records did not fit
+FILL_STAGE = "k_radius_fill_rec + k_radius_fill_rec_long + k_radius_fill"
 CURVES = ("morton", "hilbert")
 KERNELS = ("sphere", "cube")
 RADII = (0.5, 1.0, 2.0, 3.0)
@@ -45,6 +51,9 @@ def parse():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=100_000, help="queries per (kernel, r) for the oracle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-record", action="store_true",
+                    help="radius: the fill searches again instead of writing rows from the hits the count "
+                         "pass recorded (SFC_RECORD_HITS, the default)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--workload", default="radius", choices=["radius", "batched", "served", "subset"],
@@ -430,6 +439,8 @@ def main():
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
     indices = torch.empty(cap, dtype=torch.int32, device="cuda")
     need = ctypes.c_size_t(0)
+    record = not args.no_record
+    rf = B.RECORD_HITS if record else 0
 
     def fill_events():
         return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -449,17 +460,17 @@ def main():
                     base = (ctypes.byref(tree.view), None, n, sfc.KERNELS[k], float(r),
                             ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(offsets.data_ptr()))
                     if need.value == 0:
-                        B.check(L.radius_search(*base, None, 0, 0, None, ctypes.byref(need), None), "size")
+                        B.check(L.radius_search(*base, None, 0, rf, None, ctypes.byref(need), None), "size")
                         step.ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
                     ws = ctypes.c_void_p(step.ws.data_ptr())
                     # count pass + scan
-                    B.check(L.radius_search(*base, None, 0, 0, ws, ctypes.byref(need), ctypes.c_void_p(sp)),
+                    B.check(L.radius_search(*base, None, 0, rf, ws, ctypes.byref(need), ctypes.c_void_p(sp)),
                             "radius count")
                     if events is not None:
                         events[i][0].record(stream)
                     # fill pass only (counts/offsets from the call above)
-                    B.check(L.radius_search(*base, ctypes.c_void_p(indices.data_ptr()), cap, B.REUSE_COUNTS, ws,
-                                            ctypes.byref(need), ctypes.c_void_p(sp)), "radius fill")
+                    B.check(L.radius_search(*base, ctypes.c_void_p(indices.data_ptr()), cap, B.REUSE_COUNTS | rf,
+                                            ws, ctypes.byref(need), ctypes.c_void_p(sp)), "radius fill")
                     if events is not None:
                         events[i][1].record(stream)
                     i += 1
@@ -489,7 +500,11 @@ def main():
     build_ms = {c: float(np.mean([ev_build[s][i][0].elapsed_time(ev_build[s][i][1]) for s in range(args.steps)]))
                 for i, c in enumerate(CURVES)}
 
+    # algorithmic bytes of one fill stage: the row offsets read and the indices
+    # written; the search fill must also read every point and node once
     def alg_bytes(c, total):
+        if record:
+            return 8 * (n + 1) + 4 * total
         return 16 * n + 8 * (n + 1) + 4 * total + 36 * infos[c]["n_nodes"]
 
     tot_bytes = 0.0
@@ -504,12 +519,13 @@ def main():
         detail[f"{c}/{k}/r={r}"] = {"mu": totals[cb] / n, "fill_ms": round(ms, 4),
                                     "fill_GBps": round(b / ms / 1e6, 1)}
     achieved = tot_bytes / tot_ms / 1e6  # GB/s
-    # measured HBM bytes per fill launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid only
+    # measured HBM bytes per fill stage (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid only
     # while the kernel source is the one the counters were taken on
     traffic = None
     try:
         from paper_2603_06771_amd import rocprof_summary
-        rec = json.load(open(os.path.join(ROOT, "profiles", "k_radius_fill_lidar10M_traffic.json")))
+        name = "radius_fill_stage_record_lidar10M_traffic.json" if record else "k_radius_fill_lidar10M_traffic.json"
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
         src = os.path.join(ROOT, "paper_2603_06771_amd", "csrc", "search.hip")
         if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 64 and n == 10_000_000:
             traffic = rec["bytes_per_launch"]
@@ -533,8 +549,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lidar_tile_10M_radius_sweep", "points": n, "curves": list(CURVES),
                    "kernels": list(KERNELS), "radii_m": list(RADII), "leaf_size": args.leaf,
-                   "queries_per_step": queries_per_step, "builds_per_step": len(CURVES)},
-        "roofline": {"bound": "hbm", "kernel": "k_radius_fill", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                   "queries_per_step": queries_per_step, "builds_per_step": len(CURVES),
+                   "record_hits": record},
+        "roofline": {"bound": "hbm", "kernel": FILL_STAGE if record else "k_radius_fill", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": tot_bytes / len(combos)},
         "build_ms": {c: round(v, 3) for c, v in build_ms.items()},

@@ -158,10 +158,21 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
  *             by their code in the tree's frame inside the call (workspace
  *             grows by about 24 bytes per query); rows of the output always
  *             follow the caller's query order.
+ *             bit 3 (SFC_RECORD_HITS): the count pass records, for every
+ *             group of 64 queries, each tested point that is a neighbour of
+ *             one of them (its index and the mask of those queries), and
+ *             the fill writes the rows from these records instead of
+ *             searching again; a group whose records do not fit (more than
+ *             4096) is filled by the search.  The workspace grows by about
+ *             48 KB per 64 queries.  With SFC_REUSE_COUNTS the
+ *             records of the preceding count call on the same workspace are
+ *             used, so both calls must pass this bit, the same workspace and
+ *             identical arguments.  The result is the same with or without it.
  */
 #define SFC_REUSE_COUNTS 1u
 #define SFC_NO_PRUNE 2u
 #define SFC_QUERIES_ORDERED 4u
+#define SFC_RECORD_HITS 8u
 int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
                   uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
                   uint32_t flags, void *ws, size_t *ws_bytes, void *stream);

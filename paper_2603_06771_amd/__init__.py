@@ -149,11 +149,13 @@ def build_linear_octree(xyz, curve="morton", bits: int = 21, leaf_size: int = 32
 
 
 def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, capacity: int | None = None,
-                  prune: bool = True):
+                  prune: bool = True, record: bool = False):
     """Section 3.2 / 5.1: CSR (counts int32, offsets int64 [nq+1], indices
     int32 original point indices).  queries=None searches around every cloud
     point, rows in sorted (curve) order.  Without a capacity the count pass
-    runs first and the host reads the total before the fill pass."""
+    runs first and the host reads the total before the fill pass.  record:
+    the fill writes rows from the hits the count pass recorded (same
+    result, larger workspace)."""
     torch = _torch()
     L = B.load()
     if queries is not None:
@@ -162,7 +164,7 @@ def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, c
     else:
         nq = tree.n
     k = _code(KERNELS, kernel)
-    flags = 0 if prune else B.NO_PRUNE
+    flags = (0 if prune else B.NO_PRUNE) | (B.RECORD_HITS if record else 0)
     counts = torch.empty(nq, dtype=torch.int32, device="cuda")
     offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)
@@ -335,11 +337,12 @@ def _query_rows(torch, batch, queries, q_sizes):
 
 
 def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphere", r=1.0,
-                          capacity: int | None = None, prune: bool = True):
+                          capacity: int | None = None, prune: bool = True, record: bool = False):
     """Radius search of every cloud of the batch (its own kernel and radius)
     in one launch per pass.  One CSR over all rows (cloud c's rows follow
     cloud c - 1's); indices are local to each cloud.  queries=None: every
-    cloud's own points, rows in each cloud's sorted order."""
+    cloud's own points, rows in each cloud's sorted order.  record: as for
+    radius_search."""
     torch = _torch()
     L = B.load()
     kernels = _per_cloud(kernel, batch.B, "kernel")
@@ -348,7 +351,7 @@ def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphe
         batch.clouds[c].kernel = _code(KERNELS, kernels[c])
         batch.clouds[c].r = float(radii[c])
     queries, nq = _query_rows(torch, batch, queries, q_sizes)
-    flags = 0 if prune else B.NO_PRUNE
+    flags = (0 if prune else B.NO_PRUNE) | (B.RECORD_HITS if record else 0)
     counts = torch.empty(nq, dtype=torch.int32, device="cuda")
     offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsfcoct.so")
 SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_ECAPACITY, SFC_EHIP, SFC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MORTON, HILBERT = 0, 1
 SPHERE, CIRCLE, CUBE, SQUARE = 0, 1, 2, 3
-REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED = 1, 2, 4
+REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED, RECORD_HITS = 1, 2, 4, 8
 
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",

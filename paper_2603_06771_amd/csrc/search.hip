@@ -29,6 +29,10 @@
 //    to its own LDS row (one byte each), and rows are flushed to HBM with
 //    coalesced half-wave stores when they fill up and at the end of every
 //    staging round.
+//  * Recorded hits (optional): the count pass also stores, per group, every
+//    staged point that hits some lane (its index and the 64-bit mask of the
+//    lanes it hits, in staging order); the fill then writes the rows from
+//    these records without traversal or distance tests, in the same order.
 //  * k-NN: lane-owned top-k (k <= 64) of (d2, index) keys in registers
 //    (descending, so the current k-th is always register 0), seeded with an
 //    upper bound of the k-th distance taken from the query's curve
@@ -62,6 +66,21 @@ namespace {
 #ifndef SFC_ROWCAP
 #define SFC_ROWCAP 32
 #endif
+#ifndef SFC_REC_CHUNKL
+#define SFC_REC_CHUNKL 8
+#endif
+#ifndef SFC_REC_BATCH
+#define SFC_REC_BATCH 4
+#endif
+#ifndef SFC_REC_LONG_MEAN
+#define SFC_REC_LONG_MEAN 64
+#endif
+#ifndef SFC_REC_CAP
+#define SFC_REC_CAP 4096
+#endif
+#ifndef SFC_REC_LINE
+#define SFC_REC_LINE 32
+#endif
 #ifndef SFC_CHUNK
 #define SFC_CHUNK 16
 #endif
@@ -72,6 +91,11 @@ constexpr int kRowCap = SFC_ROWCAP;   // fill: staged output entries per query
 constexpr int kChunk = SFC_CHUNK;     // fill: points swept between flush checks
 constexpr int kSegMax = 8;            // query segments per wave
 constexpr float kJumpSteps = 5.0f;    // radius search: segment cut distance in mean curve steps (at least)
+constexpr int kRecCap = SFC_REC_CAP;  // recorded hits per group of 64 queries
+constexpr uint32_t kRecOverflow = 0xFFFFFFFFu;        // rec_n: the group's records did not fit (or it was deferred)
+constexpr uint32_t kRecLongRows = 0x40000000u;        // rec_n flag: the group takes the long-row fill
+constexpr uint32_t kRecLongMean = SFC_REC_LONG_MEAN;  // mean row length from which a group takes it
+static_assert(kRecCap < static_cast<int>(kRecLongRows), "record count and form flag share rec_n");
 static_assert(kChunk <= kRowCap && kRowCap <= 32 && kCand >= 2 * 64 && kStage % 4 == 0 && kStage >= 64 && kStage <= 256,
               "tile parameters");
 
@@ -405,6 +429,11 @@ struct SearchArgs {
     const uint64_t *roffsets; // their row starts
     uint32_t *ranges;         // (begin, end) pairs of sorted positions
     uint64_t rcapacity;       // pairs the ranges buffer holds
+    // recorded hits (SFC_RECORD_HITS): per global group, kRecCap slots of
+    // (original index, mask of the group's queries it is a neighbour of)
+    uint32_t *rec_idx;
+    uint64_t *rec_mask;
+    uint32_t *rec_n;          // records of each group; kRecOverflow: did not fit
 };
 
 // Query of a lane (position lr in its cloud's rows) and the global row its
@@ -727,7 +756,15 @@ __device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, con
     return node;
 }
 
-template <int KERNEL>
+// With REC (SFC_RECORD_HITS) the wave also records, per staged point that
+// is a neighbour of at least one of its queries, the point's original index
+// and the mask of those queries, in staging order, into the group's region
+// of the workspace: k_radius_fill_rec then writes the rows from the records
+// alone.  Every touched node is staged and tested (a contained node is not
+// counted from its size), so the records hold every neighbour in the order
+// k_radius_fill would write them.  A group whose records do not fit kRecCap,
+// or that is deferred, is marked kRecOverflow and left to k_radius_fill.
+template <int KERNEL, bool REC>
 __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;  // position within the cloud's rows
@@ -735,13 +772,18 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
     const Query q = lane_query(a, C, lr, &row);
     const float r = C.r, r2 = fmul(r, r);
     const bool prune = !(a.flags & SFC_NO_PRUNE);
+    const int64_t gg = lg + C.g0;  // global group
     uint32_t cnt = 0;
     int sid = 0;
     const int nseg = r > 0.0f ? make_segments(L, q, 2.0f * r, &sid, kJumpSteps) : 0;
     if (r > 0.0f && may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
-        defer_group(a, lg + C.g0);
+        if constexpr (REC) {
+            if (lane == 0) a.rec_n[gg] = kRecOverflow;
+        }
+        defer_group(a, gg);
         return;
     }
+    uint32_t nrec = 0;  // records of the group so far (may pass kRecCap: then none is kept)
     if (r > 0.0f) {
         // every lane tests its query against the staged points
         auto body = [&](uint32_t n_) {
@@ -756,6 +798,43 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
             }
             for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
         };
+        // recording: lane j of (mlo, mhi) takes the query mask of staged point
+        // t0 + j; per 64 points the ones with a neighbour are compacted and
+        // stored (lane = record: coalesced)
+        const float qx = q.valid ? q.x : INFINITY, qy = q.valid ? q.y : INFINITY, qz = q.valid ? q.z : INFINITY;
+        uint32_t *const ridx = a.rec_idx + gg * kRecCap;
+        uint64_t *const rmask = a.rec_mask + gg * kRecCap;
+        auto body_rec = [&](uint32_t n_) {
+            const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
+            for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
+                const uint32_t te = min(n, t0 + kWave);
+                uint32_t mlo = 0, mhi = 0;
+                uint32_t t = t0;
+                auto test = [&](uint32_t u) {
+                    const bool h = point_hit<KERNEL>(L.pts[u], qx, qy, qz, r, r2);
+                    cnt += h ? 1u : 0u;
+                    const uint64_t m = ballot(h);
+                    const bool mine = static_cast<uint32_t>(lane) == u - t0;
+                    mlo = mine ? static_cast<uint32_t>(m) : mlo;
+                    mhi = mine ? static_cast<uint32_t>(m >> 32) : mhi;
+                };
+                for (; t + 4 <= te; t += 4) {
+                    test(t);
+                    test(t + 1);
+                    test(t + 2);
+                    test(t + 3);
+                }
+                for (; t < te; ++t) test(t);
+                const bool keep = static_cast<uint32_t>(lane) < te - t0 && (mlo | mhi) != 0u;
+                const uint64_t km = ballot(keep);
+                const uint32_t at = nrec + static_cast<uint32_t>(rank_below(km));
+                if (keep && at < static_cast<uint32_t>(kRecCap)) {
+                    ridx[at] = __float_as_uint(L.pts[t0 + lane].w);
+                    rmask[at] = (static_cast<uint64_t>(mhi) << 32) | mlo;
+                }
+                nrec += static_cast<uint32_t>(__popcll(km));
+            }
+        };
         uint32_t staged = 0;  // points staged and not yet swept, across candidate batches
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
@@ -764,19 +843,240 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 uint64_t mixed, touched, full;
                 const uint32_t len =
                     classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
-                // contained for my segment and not swept: count the whole node
-                for (uint64_t b = full & ~mixed; b; b &= b - 1) cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
-                if (!mixed) continue;
-                stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, body, &staged);
+                if constexpr (REC) {
+                    if (!touched) continue;
+                    stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, body_rec, &staged);
+                } else {
+                    // contained for my segment and not swept: count the whole node
+                    for (uint64_t b = full & ~mixed; b; b &= b - 1)
+                        cnt += L.clen[__ffsll(static_cast<long long>(b)) - 1];
+                    if (!mixed) continue;
+                    stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, body, &staged);
+                }
             }
         };
         traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
         if (staged) {
             wave_sync();
-            body(staged);
+            if constexpr (REC)
+                body_rec(staged);
+            else
+                body(staged);
         }
     }
     if (q.valid) a.counts[row] = cnt;
+    if constexpr (REC) {
+        // rows averaging a line or more take the long-row form
+        const uint32_t hits = __shfl(wave_inclusive_sum(q.valid ? cnt : 0u), kWave - 1);
+        const uint32_t nvalid = static_cast<uint32_t>(__popcll(ballot(q.valid)));
+        const uint32_t form = hits >= kRecLongMean * nvalid ? kRecLongRows : 0u;
+        if (lane == 0) a.rec_n[gg] = nrec <= static_cast<uint32_t>(kRecCap) ? (nrec | form) : kRecOverflow;
+    }
+}
+
+// Writing the rows of a group from its records (SFC_RECORD_HITS): per
+// record, every lane whose bit is set appends the record to its LDS row.
+// No traversal and no distance test.  Two forms, chosen per group by the
+// count pass from the group's mean row length:
+//  - short rows: rows hold one-byte slots into the current chunk of 64
+//    records and are written out (two rows per step, one per half wave) once
+//    they could overflow and after every chunk;
+//  - long rows: rows hold indices and outlive chunks; a row is written out
+//    up to the next 128-byte boundary of its output once it reaches it, so
+//    every store but a row's first and last is one whole aligned line.
+constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written per aligned run
+constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
+constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
+constexpr int kRecBatch = SFC_REC_BATCH;         // chunks of 64 records loaded per round trip
+static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 8 && kRecLine <= 32 &&
+                  (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
+              "record fill shapes");
+
+struct RecLds {
+    uint8_t rows[kWave * (kRowCap + 1)];
+    uint64_t fpos[kWave];
+    uint8_t flim[kWave];
+    uint8_t flist[kWave];
+    uint32_t pidx[kWave];  // original indices of the chunk's records
+};
+
+__device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs &a, const SearchCloud &C,
+                                                     int64_t lg, uint32_t n) {
+    const int lane = lane_id();
+    const int64_t lr = lg * kWave + lane;
+    const int64_t gg = lg + C.g0;
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
+    const int64_t orow = q.valid ? row : 0;
+    const uint64_t o0 = a.offsets[orow], o1 = a.offsets[orow + 1];
+    uint64_t gpos = q.valid ? o0 : 0ull;
+    const uint64_t gend = q.valid ? o1 : 0ull;
+    uint64_t left = gend > gpos ? gend - gpos : 0ull;
+    uint32_t nb = 0;
+    uint8_t *myrow = L.rows + lane * (kRowCap + 1);
+    uint32_t *out = a.indices;
+    const int half = lane >> 5, hl = lane & 31;
+    auto flush = [&](uint32_t limit) {
+        const bool go = nb > limit;
+        const uint64_t fm = ballot(go);
+        if (!fm) return;
+        const int nf = __popcll(fm);
+        if (go) {
+            L.fpos[lane] = gpos;
+            L.flim[lane] = static_cast<uint8_t>(left < nb ? left : nb);
+            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+        }
+        wave_sync();
+        for (int i0 = 0; i0 < nf; i0 += 2) {
+            const int i = i0 + half;
+            if (i < nf) {
+                const int l = L.flist[i];
+                if (hl < L.flim[l]) out[L.fpos[l] + hl] = L.pidx[L.rows[l * (kRowCap + 1) + hl]];
+            }
+        }
+        if (go) {
+            gpos += nb;
+            left -= left < nb ? left : nb;
+            nb = 0;
+        }
+        wave_sync();
+    };
+    const uint32_t *ridx = a.rec_idx + gg * kRecCap;
+    const uint64_t *rmask = a.rec_mask + gg * kRecCap;
+    // kRecBatch chunks of 64 records per round trip (lane = record of each chunk)
+    for (uint32_t b0 = 0; b0 < n; b0 += kRecBatch * kWave) {
+        uint32_t bpi[kRecBatch], blo[kRecBatch], bhi[kRecBatch];
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const uint32_t k = b0 + u * kWave + lane;
+            const bool have = k < n;
+            const uint64_t pm = have ? rmask[k] : 0ull;
+            bpi[u] = have ? ridx[k] : 0u;
+            blo[u] = static_cast<uint32_t>(pm);
+            bhi[u] = static_cast<uint32_t>(pm >> 32);
+        }
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const uint32_t c0 = b0 + u * kWave;
+            if (c0 >= n) break;
+            const uint32_t m = min(n - c0, static_cast<uint32_t>(kWave));
+            L.pidx[lane] = bpi[u];  // the previous chunk's rows were written (and read) already
+            const uint32_t lo = blo[u], hi = bhi[u];
+            for (uint32_t j0 = 0; j0 < m; j0 += kChunk) {
+                flush(kRowCap - kChunk);
+                const uint32_t je = min(m, j0 + kChunk);
+                uint8_t *w = myrow + nb;
+#pragma unroll 4
+                for (uint32_t j = j0; j < je; ++j) {
+                    const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
+                                        readlane_u32(lo, static_cast<int>(j));
+                    *w = static_cast<uint8_t>(j);
+                    w += static_cast<uint32_t>(mk >> lane) & 1u;
+                }
+                nb = static_cast<uint32_t>(w - myrow);
+            }
+            flush(0);  // the rows point into this chunk's records
+        }
+    }
+}
+
+struct RecLdsLong {
+    uint32_t rows[kWave * (kRecRowL + 1)];  // odd stride: appends at different lengths spread over banks
+    uint64_t fpos[kWave];
+    uint8_t fcnt[kWave];   // entries written out (clamped to the row's end)
+    uint8_t fdrop[kWave];  // entries taken off the row
+    uint8_t frem[kWave];   // entries left, moved to the row's start
+    uint8_t flist[kWave];
+};
+
+__device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const SearchArgs &a, const SearchCloud &C,
+                                                          int64_t lg, uint32_t n) {
+    constexpr int kStride = kRecRowL + 1;
+    const int lane = lane_id();
+    const int64_t lr = lg * kWave + lane;
+    const int64_t gg = lg + C.g0;
+    int64_t row;
+    const Query q = lane_query(a, C, lr, &row);
+    const int64_t orow = q.valid ? row : 0;
+    const uint64_t o0 = a.offsets[orow], o1 = a.offsets[orow + 1];
+    uint64_t gpos = q.valid ? o0 : 0ull;
+    const uint64_t gend = q.valid ? o1 : 0ull;
+    uint64_t left = gend > gpos ? gend - gpos : 0ull;
+    uint32_t nb = 0;
+    uint32_t *myrow = L.rows + lane * kStride;
+    uint32_t *out = a.indices;
+    const int half = lane >> 5, hl = lane & 31;
+    // all: write every entry; else only rows that reach their next line
+    // boundary, up to it.  Kept entries move to the row's start in the same
+    // step (each lane reads its entry before any lane writes).
+    auto flush = [&](bool all) {
+        const uint32_t to_line = kRecLine - static_cast<uint32_t>(gpos & (kRecLine - 1));
+        const uint32_t drop = all ? nb : (nb >= to_line ? to_line : 0u);
+        const bool go = drop > 0;
+        const uint64_t fm = ballot(go);
+        if (!fm) return;
+        const int nf = __popcll(fm);
+        if (go) {
+            L.fpos[lane] = gpos;
+            L.fcnt[lane] = static_cast<uint8_t>(left < drop ? left : drop);
+            L.fdrop[lane] = static_cast<uint8_t>(drop);
+            L.frem[lane] = static_cast<uint8_t>(nb - drop);
+            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+        }
+        wave_sync();
+        for (int i0 = 0; i0 < nf; i0 += 2) {
+            const int i = i0 + half;
+            if (i < nf) {
+                const int l = L.flist[i];
+                uint32_t *rw = L.rows + l * kStride;
+                const uint32_t keep = hl < L.frem[l] ? rw[L.fdrop[l] + hl] : 0u;
+                if (hl < L.fcnt[l]) out[L.fpos[l] + hl] = rw[hl];
+                if (hl < L.frem[l]) rw[hl] = keep;
+            }
+        }
+        if (go) {
+            gpos += drop;
+            left -= left < drop ? left : drop;
+            nb -= drop;
+        }
+        wave_sync();
+    };
+    const uint32_t *ridx = a.rec_idx + gg * kRecCap;
+    const uint64_t *rmask = a.rec_mask + gg * kRecCap;
+    for (uint32_t b0 = 0; b0 < n; b0 += kRecBatch * kWave) {
+        uint32_t bpi[kRecBatch], blo[kRecBatch], bhi[kRecBatch];
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const uint32_t k = b0 + u * kWave + lane;
+            const bool have = k < n;
+            const uint64_t pm = have ? rmask[k] : 0ull;
+            bpi[u] = have ? ridx[k] : 0u;
+            blo[u] = static_cast<uint32_t>(pm);
+            bhi[u] = static_cast<uint32_t>(pm >> 32);
+        }
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const uint32_t c0 = b0 + u * kWave;
+            if (c0 >= n) break;
+            const uint32_t m = min(n - c0, static_cast<uint32_t>(kWave));
+            const uint32_t pi = bpi[u], lo = blo[u], hi = bhi[u];
+            for (uint32_t j0 = 0; j0 < m; j0 += kRecChunkL) {
+                flush(false);  // afterwards nb < kRecLine, so the chunk fits
+                const uint32_t je = min(m, j0 + kRecChunkL);
+                uint32_t *w = myrow + nb;
+#pragma unroll 4
+                for (uint32_t j = j0; j < je; ++j) {
+                    const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
+                                        readlane_u32(lo, static_cast<int>(j));
+                    *w = readlane_u32(pi, static_cast<int>(j));
+                    w += static_cast<uint32_t>(mk >> lane) & 1u;
+                }
+                nb = static_cast<uint32_t>(w - myrow);
+            }
+        }
+    }
+    flush(false);  // a row may hold up to kRecRowL entries; afterwards fewer than kRecLine,
+    flush(true);   // which one half wave writes
 }
 
 // One query's row [pos, end): contained candidates are copied from the
@@ -1080,11 +1380,53 @@ __global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) {
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.kernel) {
-    case SFC_SPHERE: radius_count_body<SFC_SPHERE>(L, a, C, lg); break;
-    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE>(L, a, C, lg); break;
-    case SFC_CUBE: radius_count_body<SFC_CUBE>(L, a, C, lg); break;
-    default: radius_count_body<SFC_SQUARE>(L, a, C, lg); break;
+    case SFC_SPHERE: radius_count_body<SFC_SPHERE, false>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE, false>(L, a, C, lg); break;
+    case SFC_CUBE: radius_count_body<SFC_CUBE, false>(L, a, C, lg); break;
+    default: radius_count_body<SFC_SQUARE, false>(L, a, C, lg); break;
     }
+}
+
+// the count that also records every group's hits (SFC_RECORD_HITS)
+__global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
+    __shared__ RadLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    const int64_t lg = g - C.g0;
+    switch (C.kernel) {
+    case SFC_SPHERE: radius_count_body<SFC_SPHERE, true>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE, true>(L, a, C, lg); break;
+    case SFC_CUBE: radius_count_body<SFC_CUBE, true>(L, a, C, lg); break;
+    default: radius_count_body<SFC_SQUARE, true>(L, a, C, lg); break;
+    }
+}
+
+// rows of the recorded groups in the short-row form; the others are left to
+// k_radius_fill_rec_long and (records that did not fit) k_radius_fill
+__global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
+    __shared__ RecLds L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    if (v == kRecOverflow || (v & kRecLongRows)) return;
+    const SearchCloud C = group_cloud(a, g);
+    if (!(C.r > 0.0f)) return;  // empty rows
+    radius_fill_rec_body(L, a, C, g - C.g0, min(v, static_cast<uint32_t>(kRecCap)));
+}
+
+// rows of the recorded groups in the long-row form
+__global__ __launch_bounds__(64) void k_radius_fill_rec_long(SearchArgs a) {
+    __shared__ RecLdsLong L;
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    if (v == kRecOverflow || !(v & kRecLongRows)) return;
+    const SearchCloud C = group_cloud(a, g);
+    if (!(C.r > 0.0f)) return;  // empty rows
+    radius_fill_rec_long_body(L, a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
 }
 
 __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
@@ -1092,6 +1434,7 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    if (a.rec_n && a.rec_n[g] != kRecOverflow) return;  // written from its records
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.kernel) {
@@ -1680,13 +2023,16 @@ struct SearchWs {
     int64_t *starts = nullptr;
     uint32_t *spread = nullptr;
     uint32_t *nspread = nullptr;
+    uint32_t *rec_idx = nullptr;
+    uint64_t *rec_mask = nullptr;
+    uint32_t *rec_n = nullptr;
 };
 
 bool wants_order(const float *queries, int64_t nq_total, uint32_t flags) {
     return queries && !(flags & SFC_QUERIES_ORDERED) && nq_total > kWave;
 }
 
-size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem, SearchWs *w) {
+size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem, SearchWs *w, bool record = false) {
     Carver c(mem);
     SearchWs x;
     if (B > 1) x.tab = c.take<SearchCloud>(B);
@@ -1702,13 +2048,19 @@ size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem
         x.radix = c.take<char>(radix_ws_bytes(nq_total));
         x.starts = c.take<int64_t>(B + 1);
     }
+    if (record) {
+        const int64_t groups = nq_total / kWave + B + 1;
+        x.rec_idx = c.take<uint32_t>(groups * kRecCap);
+        x.rec_mask = c.take<uint64_t>(groups * kRecCap);
+        x.rec_n = c.take<uint32_t>(groups);
+    }
     c.take<char>(256);
     if (w) *w = x;
     return c.bytes();
 }
 
-size_t search_ws_bytes(int B, int64_t nq_total, bool scan, bool order = false) {
-    return carve_search_ws(B, nq_total, scan, order, nullptr, nullptr);
+size_t search_ws_bytes(int B, int64_t nq_total, bool scan, bool order = false, bool record = false) {
+    return carve_search_ws(B, nq_total, scan, order, nullptr, nullptr, record);
 }
 
 // Sorts the external queries of every cloud by their code (stable, so equal
@@ -1733,8 +2085,14 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
                   void *ws, hipStream_t s) {
     const int B = static_cast<int>(tab.size());
     const bool order = wants_order(a.queries, a.nq_total, a.flags);
+    const bool record = (a.flags & SFC_RECORD_HITS) != 0;
     SearchWs w;
-    carve_search_ws(B, a.nq_total, true, order, ws, &w);
+    carve_search_ws(B, a.nq_total, true, order, ws, &w, record);
+    if (record) {
+        a.rec_idx = w.rec_idx;
+        a.rec_mask = w.rec_mask;
+        a.rec_n = w.rec_n;
+    }
     SearchCloud *dtab = w.tab;
     void *scan_ws = w.scan;
     a.one = tab[0];
@@ -1760,8 +2118,13 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
                 k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
                 SFC_LAUNCH_CHECK("k_reset_spread");
             }
-            k_radius_count<<<grid, 64, 0, s>>>(a);
-            SFC_LAUNCH_CHECK("k_radius_count");
+            if (record) {
+                k_radius_count_rec<<<grid, 64, 0, s>>>(a);
+                SFC_LAUNCH_CHECK("k_radius_count_rec");
+            } else {
+                k_radius_count<<<grid, 64, 0, s>>>(a);
+                SFC_LAUNCH_CHECK("k_radius_count");
+            }
             if (a.queries) {  // only external queries are ever deferred
                 k_radius_count_spread<<<sgrid, 64, 0, s>>>(a);
                 SFC_LAUNCH_CHECK("k_radius_count_spread");
@@ -1774,6 +2137,12 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
         if (a.queries) {
             k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
             SFC_LAUNCH_CHECK("k_reset_spread");
+        }
+        if (record) {
+            k_radius_fill_rec<<<grid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_fill_rec");
+            k_radius_fill_rec_long<<<grid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_fill_rec_long");
         }
         k_radius_fill<<<grid, 64, 0, s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");
@@ -1850,7 +2219,7 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         set_error("radius_search: invalid argument");
         return SFC_EINVAL;
     }
-    const size_t need = search_ws_bytes(1, nq, true, wants_order(queries, nq, flags));
+    const size_t need = search_ws_bytes(1, nq, true, wants_order(queries, nq, flags), (flags & SFC_RECORD_HITS) != 0);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -1960,7 +2329,8 @@ extern "C" int radius_search_batched(int B, const sfc_cloud *clouds, const float
     std::vector<SearchCloud> tab;
     const int64_t groups = search_table("radius_search_batched", B, clouds, queries, nq_total, false, 0, tab);
     if (groups < 0) return SFC_EINVAL;
-    const size_t need = search_ws_bytes(B, nq_total, true, wants_order(queries, nq_total, flags));
+    const size_t need =
+        search_ws_bytes(B, nq_total, true, wants_order(queries, nq_total, flags), (flags & SFC_RECORD_HITS) != 0);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;

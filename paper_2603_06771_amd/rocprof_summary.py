@@ -7,6 +7,8 @@
     python -m paper_2603_06771_amd.rocprof_summary lds <counter_collection.csv> <kernel-name>
     python -m paper_2603_06771_amd.rocprof_summary traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> [kernel-substring]
+    python -m paper_2603_06771_amd.rocprof_summary record <fetch.csv> <write.csv> <kernel> <source>
+    python -m paper_2603_06771_amd.rocprof_summary stage <fetch.csv> <write.csv> <k1,k2,...> <stages> <source>
 
 `traffic` reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the matching
 kernel, scaled by what the same counters read for the plain device copy of
@@ -184,6 +186,35 @@ def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, m
             "fetch_scale": ffac, "write_scale": wfac}
 
 
+def _base(kernel_name: str) -> str:
+    return kernel_name.split("(")[0].split("::")[-1]
+
+
+def stage_record(fetch_path: str, write_path: str, kernels: list, stages: int, source: str) -> dict:
+    """Scaled HBM bytes of a stage made of several kernels (exact base names):
+    the sum over every dispatch of those kernels in the run, divided by the
+    number of stages the run executed; tagged like traffic_record."""
+    fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
+    write = _per_dispatch(write_path, "WRITE_SIZE")
+    fc = max(v for _, k, v in fetch if "copyBuffer" in k)
+    wc = max(v for _, k, v in write if "copyBuffer" in k)
+    half = COPY_BYTES // 2
+    ffac, wfac = half / (fc * 1024), half / (wc * 1024)
+    names = set(kernels)
+    f_sum = sum(v for _, k, v in fetch if _base(k) in names) * 1024 * ffac
+    w_sum = sum(v for _, k, v in write if _base(k) in names) * 1024 * wfac
+    per = {}
+    for _, k, v in fetch:
+        if _base(k) in names:
+            per.setdefault(_base(k), [0, 0.0])
+            per[_base(k)][0] += 1
+            per[_base(k)][1] += v * 1024 * ffac
+    return {"kernels": sorted(names), "source_sha": source_sha(source), "stages": stages,
+            "fetch_bytes_per_launch": f_sum / stages, "write_bytes_per_launch": w_sum / stages,
+            "bytes_per_launch": (f_sum + w_sum) / stages, "fetch_scale": ffac, "write_scale": wfac,
+            "fetch_bytes_by_kernel": {k: {"dispatches": c, "bytes_per_stage": b / stages} for k, (c, b) in per.items()}}
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
@@ -195,6 +226,10 @@ if __name__ == "__main__":
         print(sq(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "trace":
         print(trace(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else 100.0))
+    elif sys.argv[1] == "stage":
+        import json
+        print(json.dumps(stage_record(sys.argv[2], sys.argv[3], sys.argv[4].split(","), int(sys.argv[5]),
+                                      sys.argv[6]), indent=1))
     elif sys.argv[1] == "record":
         import json
         print(json.dumps(traffic_record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5]), indent=1))

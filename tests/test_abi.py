@@ -142,3 +142,29 @@ def test_gather_points_validation(lib):
     assert lib.gather_points(fake, 10, fake, 0, fake, None) == B.SFC_OK  # nothing to do, nothing launched
     assert lib.gather_points(fake, 10, None, 5, fake, None) == B.SFC_EINVAL
     assert lib.gather_points(fake, -1, fake, 5, fake, None) == B.SFC_EINVAL
+
+
+def test_flag_constants_match_header():
+    text = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SFC_([A-Z_]+) (\d+)u", text)}
+    assert defs["REUSE_COUNTS"] == B.REUSE_COUNTS and defs["NO_PRUNE"] == B.NO_PRUNE
+    assert defs["QUERIES_ORDERED"] == B.QUERIES_ORDERED and defs["RECORD_HITS"] == B.RECORD_HITS
+    assert len({B.REUSE_COUNTS, B.NO_PRUNE, B.QUERIES_ORDERED, B.RECORD_HITS}) == 4
+
+
+def test_record_hits_workspace_size(lib):
+    # recording adds one region per group of 64 queries (4096 records of a
+    # 4-byte index and an 8-byte mask, plus the group's record count)
+    view = B.SfcOctree()
+    view.nodes = view.child = view.points = view.keys = view.frame = 256
+    fake = ctypes.c_void_p(256)
+    for n in (10, 64, 65, 100_000):
+        view.n = n
+        plain, rec = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        assert lib.radius_search(ctypes.byref(view), None, n, 0, 1.0, fake, fake, None, 0, 0, None,
+                                 ctypes.byref(plain), None) == B.SFC_OK
+        assert lib.radius_search(ctypes.byref(view), None, n, 0, 1.0, fake, fake, None, 0, B.RECORD_HITS, None,
+                                 ctypes.byref(rec), None) == B.SFC_OK
+        groups = (n + 63) // 64
+        assert rec.value - plain.value >= groups * 4096 * 12 + groups * 4
+        assert rec.value - plain.value <= (n // 64 + 2) * (4096 * 12 + 4) + 3 * 256

@@ -1,0 +1,133 @@
+"""GPU parity of the recorded-hits fill (SFC_RECORD_HITS): the count pass
+records every group's neighbours and the fill writes the rows from those
+records.  Each case checks the rows against the oracle and against the
+search fill, entry for entry (same order inside every row), through both call
+forms: count then fill on the same workspace, and one call with a capacity.
+Cases cover groups whose records overflow the per-group limit (left to the
+search fill), deferred groups of sparse external queries, and batches."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_06771_amd import datagen
+from tests._parity import announce, assert_csr_equal
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ["sphere", "circle", "cube", "square"]
+
+
+@pytest.fixture(scope="module")
+def sfc():
+    import torch  # noqa: F401
+    import paper_2603_06771_amd as sfc
+    return sfc
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)).cuda()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _same(a, b, what):
+    for x, y, name in zip(a, b, ("counts", "offsets", "indices")):
+        assert np.array_equal(_np(x), _np(y)), f"{what}: {name} differ"
+
+
+def _rec_case(sfc, pts, curve, leaf, kernel, r, queries=None, prune=True, oracle_check=True):
+    import torch
+    t = sfc.build_linear_octree(_dev(pts), curve, 21, leaf)
+    q = None if queries is None else _dev(queries)
+    what = f"{kernel} r={r} prune={prune}"
+    base = sfc.radius_search(t, q, kernel, r, prune=prune)
+    rec = sfc.radius_search(t, q, kernel, r, prune=prune, record=True)
+    torch.cuda.synchronize()
+    _same(base, rec, what + " (count, then fill from records)")
+    total = int(base[1][-1])
+    one = sfc.radius_search(t, q, kernel, r, capacity=max(total, 1), prune=prune, record=True)
+    torch.cuda.synchronize()
+    _same(base[:2], one[:2], what + " (one call)")
+    assert np.array_equal(_np(base[2])[:total], _np(one[2])[:total]), what + " (one call): indices differ"
+    if oracle_check:
+        perm = t.perm().cpu().numpy().view(np.uint32)
+        qpts = pts[perm] if queries is None else queries
+        ref = oracle.radius_search(pts, qpts, kernel, r)
+        assert_csr_equal((_np(rec[0]), _np(rec[1]), _np(rec[2])), ref, what)
+    return rec
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("curve", ["morton", "hilbert"])
+def test_record_lidar(sfc, kernel, curve):
+    pts = datagen.lidar_tile(60001, seed=11)
+    for r in (0.5, 1.0, 3.0):
+        announce(f"record lidar {kernel} {curve} r={r}")
+        _rec_case(sfc, pts, curve, 32, kernel, r)
+
+
+def test_record_overflow_mixed(sfc):
+    # a dense blob (thousands of neighbours per query: every group's records
+    # overflow) beside a sparse cloud (few records per group), in one call
+    rng = np.random.default_rng(51)
+    dense = rng.uniform(0.0, 1.0, (8000, 3)).astype(np.float32)
+    sparse = rng.uniform(2.0, 60.0, (30000, 3)).astype(np.float32)
+    pts = np.concatenate([dense, sparse])
+    for kernel, r in (("sphere", 0.45), ("cube", 0.35)):
+        announce(f"record overflow mixed {kernel}")
+        c, o, i = _rec_case(sfc, pts, "hilbert", 32, kernel, r)
+        assert int(c.max()) > 2048  # a group holding this query cannot be recorded
+
+
+def test_record_no_prune_and_leaves(sfc):
+    pts = datagen.with_duplicates(datagen.uniform(17500, seed=5), 2500, seed=5)
+    for leaf in (1, 64, 200):
+        announce(f"record dup leaf={leaf}")
+        _rec_case(sfc, pts, "hilbert", leaf, "sphere", 0.03)
+    announce("record no-prune")
+    _rec_case(sfc, datagen.lidar_tile(30000, seed=9), "morton", 16, "sphere", 2.5, prune=False)
+
+
+def test_record_external_and_sparse_queries(sfc):
+    # external queries in the caller's (random) order, including far-apart
+    # ones whose groups are deferred to the one-query kernels
+    rng = np.random.default_rng(21)
+    pts = datagen.lidar_tile(100000, seed=22)
+    sub = pts[np.sort(rng.choice(pts.shape[0], 700, replace=False))]
+    lo, hi = pts.min(0), pts.max(0)
+    off = (lo + (hi - lo) * rng.uniform(-0.05, 1.05, (300, 3))).astype(np.float32)
+    dense = (lo + (hi - lo) * rng.uniform(0.0, 1.0, (6000, 3))).astype(np.float32)
+    q = np.concatenate([sub, off, dense]).astype(np.float32)
+    rng.shuffle(q)
+    for kernel in KERNELS:
+        for r in (0.3, 3.0):
+            announce(f"record external {kernel} r={r}")
+            _rec_case(sfc, pts, "hilbert", 16, kernel, r, queries=q)
+
+
+def test_record_degenerate(sfc):
+    same = np.tile(np.array([[3.25, -1.5, 7.0]], np.float32), (3000, 1))
+    one = np.array([[0.5, 0.5, 0.5]], np.float32)
+    for name, pts in (("same", same), ("one", one)):
+        announce(f"record degenerate {name}")
+        _rec_case(sfc, pts, "hilbert", 16, "sphere", 0.3)
+    announce("record r=0")
+    _rec_case(sfc, datagen.uniform(3000, seed=2), "morton", 8, "cube", 0.0)
+
+
+def test_record_batched(sfc):
+    import torch
+    sizes = [20011, 0, 1, 5003, 30011, 7]
+    clouds = [datagen.lidar_tile(n, seed=60 + i) if n else np.zeros((0, 3), np.float32)
+              for i, n in enumerate(sizes)]
+    batch = sfc.build_batch(_dev(np.concatenate(clouds)), sizes, "hilbert", 21, 16)
+    kernels = ["sphere", "cube", "circle", "square", "sphere", "cube"]
+    radii = [1.0, 2.0, 0.5, 3.0, 0.0, 1.5]
+    announce("record batched")
+    base = sfc.radius_search_batched(batch, None, None, kernels, radii)
+    rec = sfc.radius_search_batched(batch, None, None, kernels, radii, record=True)
+    torch.cuda.synchronize()
+    _same(base, rec, "batched")

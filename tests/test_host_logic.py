@@ -104,3 +104,31 @@ def test_source_sha_ignores_comments_only(tmp_path):
     c.write_text("// header\nint f(int x) {\n    return x + 2;  // one\n}\n")
     assert source_sha(str(a)) == source_sha(str(b))
     assert source_sha(str(a)) != source_sha(str(c))
+
+
+def test_stage_record_sums_the_stage_kernels(tmp_path):
+    """Stage traffic: counters of every dispatch of the named kernels (and no
+    other), scaled by the calibration copy, divided by the stage count."""
+    from paper_2603_06771_amd.rocprof_summary import COPY_BYTES, stage_record
+    half_kib = COPY_BYTES // 2 / 1024
+    head = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+    rows_f = [(1, "__amd_rocclr_copyBuffer", half_kib / 2),  # counter reads half: scale 2
+              (2, "sfc::k_radius_fill_rec(sfc::SearchArgs)", 100.0),
+              (3, "sfc::k_radius_fill_rec_long(sfc::SearchArgs)", 300.0),
+              (4, "sfc::k_radius_fill(sfc::SearchArgs)", 50.0),
+              (5, "sfc::k_radius_count_rec(sfc::SearchArgs)", 1000.0)]
+    rows_w = [(1, "__amd_rocclr_copyBuffer", half_kib), (2, "sfc::k_radius_fill_rec(sfc::SearchArgs)", 10.0),
+              (3, "sfc::k_radius_fill_rec_long(sfc::SearchArgs)", 30.0),
+              (4, "sfc::k_radius_fill(sfc::SearchArgs)", 0.0),
+              (5, "sfc::k_radius_count_rec(sfc::SearchArgs)", 7.0)]
+    f = tmp_path / "f.csv"
+    w = tmp_path / "w.csv"
+    f.write_text(head + "".join(f"{d},\"{k}\",FETCH_SIZE,{v}\n" for d, k, v in rows_f))
+    w.write_text(head + "".join(f"{d},\"{k}\",WRITE_SIZE,{v}\n" for d, k, v in rows_w))
+    src = tmp_path / "s.hip"
+    src.write_text("int x;\n")
+    r = stage_record(str(f), str(w), ["k_radius_fill_rec", "k_radius_fill_rec_long", "k_radius_fill"], 2, str(src))
+    assert r["fetch_bytes_per_launch"] == (100.0 + 300.0 + 50.0) * 1024 * 2 / 2
+    assert r["write_bytes_per_launch"] == (10.0 + 30.0) * 1024 / 2
+    assert r["bytes_per_launch"] == r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]
+    assert r["fetch_bytes_by_kernel"]["k_radius_fill_rec_long"]["dispatches"] == 1
