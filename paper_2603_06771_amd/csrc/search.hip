@@ -892,12 +892,14 @@ static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 8 && kRecLine <
                   (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
               "record fill shapes");
 
+// Rows being written out are listed compactly: entry i holds the row's
+// output position and its lane and counts packed in one word, so a writing
+// lane fetches everything about its row with two independent LDS reads.
 struct RecLds {
     uint8_t rows[kWave * (kRowCap + 1)];
-    uint64_t fpos[kWave];
-    uint8_t flim[kWave];
-    uint8_t flist[kWave];
-    uint32_t pidx[kWave];  // original indices of the chunk's records
+    uint64_t fpos[kWave];   // by list entry: output position
+    uint32_t fmeta[kWave];  // by list entry: lane | entries to write << 8
+    uint32_t pidx[kWave];   // original indices of the chunk's records
 };
 
 __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs &a, const SearchCloud &C,
@@ -922,16 +924,18 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
         if (!fm) return;
         const int nf = __popcll(fm);
         if (go) {
-            L.fpos[lane] = gpos;
-            L.flim[lane] = static_cast<uint8_t>(left < nb ? left : nb);
-            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+            const uint32_t i = rank_below(fm);
+            L.fpos[i] = gpos;
+            L.fmeta[i] = static_cast<uint32_t>(lane) | (static_cast<uint32_t>(left < nb ? left : nb) << 8);
         }
         wave_sync();
         for (int i0 = 0; i0 < nf; i0 += 2) {
             const int i = i0 + half;
             if (i < nf) {
-                const int l = L.flist[i];
-                if (hl < L.flim[l]) out[L.fpos[l] + hl] = L.pidx[L.rows[l * (kRowCap + 1) + hl]];
+                const uint32_t meta = L.fmeta[i];
+                const uint64_t pos = L.fpos[i];
+                const uint32_t slot = L.rows[(meta & 0xFFu) * (kRowCap + 1) + hl];  // hl < kRowCap + 1
+                if (static_cast<uint32_t>(hl) < (meta >> 8)) out[pos + hl] = L.pidx[slot];
             }
         }
         if (go) {
@@ -966,12 +970,17 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
                 flush(kRowCap - kChunk);
                 const uint32_t je = min(m, j0 + kChunk);
                 uint8_t *w = myrow + nb;
-#pragma unroll 4
-                for (uint32_t j = j0; j < je; ++j) {
+                auto append = [&](uint32_t j) {
                     const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
                                         readlane_u32(lo, static_cast<int>(j));
                     *w = static_cast<uint8_t>(j);
                     w += static_cast<uint32_t>(mk >> lane) & 1u;
+                };
+                if (je - j0 == static_cast<uint32_t>(kChunk)) {
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) append(j0 + u);
+                } else {
+                    for (uint32_t j = j0; j < je; ++j) append(j);
                 }
                 nb = static_cast<uint32_t>(w - myrow);
             }
@@ -982,11 +991,8 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
 
 struct RecLdsLong {
     uint32_t rows[kWave * (kRecRowL + 1)];  // odd stride: appends at different lengths spread over banks
-    uint64_t fpos[kWave];
-    uint8_t fcnt[kWave];   // entries written out (clamped to the row's end)
-    uint8_t fdrop[kWave];  // entries taken off the row
-    uint8_t frem[kWave];   // entries left, moved to the row's start
-    uint8_t flist[kWave];
+    uint64_t fpos[kWave];   // by list entry: output position
+    uint32_t fmeta[kWave];  // by list entry: lane | written << 8 | taken off << 16 | left << 24
 };
 
 __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const SearchArgs &a, const SearchCloud &C,
@@ -1017,21 +1023,24 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
         if (!fm) return;
         const int nf = __popcll(fm);
         if (go) {
-            L.fpos[lane] = gpos;
-            L.fcnt[lane] = static_cast<uint8_t>(left < drop ? left : drop);
-            L.fdrop[lane] = static_cast<uint8_t>(drop);
-            L.frem[lane] = static_cast<uint8_t>(nb - drop);
-            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+            const uint32_t i = rank_below(fm);
+            L.fpos[i] = gpos;
+            L.fmeta[i] = static_cast<uint32_t>(lane) | (static_cast<uint32_t>(left < drop ? left : drop) << 8) |
+                         (drop << 16) | ((nb - drop) << 24);
         }
         wave_sync();
         for (int i0 = 0; i0 < nf; i0 += 2) {
             const int i = i0 + half;
             if (i < nf) {
-                const int l = L.flist[i];
-                uint32_t *rw = L.rows + l * kStride;
-                const uint32_t keep = hl < L.frem[l] ? rw[L.fdrop[l] + hl] : 0u;
-                if (hl < L.fcnt[l]) out[L.fpos[l] + hl] = rw[hl];
-                if (hl < L.frem[l]) rw[hl] = keep;
+                const uint32_t meta = L.fmeta[i];
+                const uint64_t pos = L.fpos[i];
+                uint32_t *rw = L.rows + (meta & 0xFFu) * kStride;
+                const uint32_t cnt = (meta >> 8) & 0xFFu, drop_l = (meta >> 16) & 0xFFu, rem = meta >> 24;
+                // both reads stay inside the row (hl < kRecLine < kStride; drop + hl clamped)
+                const uint32_t v = rw[hl];
+                const uint32_t keep = rw[min(drop_l + static_cast<uint32_t>(hl), static_cast<uint32_t>(kStride - 1))];
+                if (static_cast<uint32_t>(hl) < cnt) out[pos + hl] = v;
+                if (static_cast<uint32_t>(hl) < rem) rw[hl] = keep;
             }
         }
         if (go) {
@@ -1064,12 +1073,17 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
                 flush(false);  // afterwards nb < kRecLine, so the chunk fits
                 const uint32_t je = min(m, j0 + kRecChunkL);
                 uint32_t *w = myrow + nb;
-#pragma unroll 4
-                for (uint32_t j = j0; j < je; ++j) {
+                auto append = [&](uint32_t j) {
                     const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
                                         readlane_u32(lo, static_cast<int>(j));
                     *w = readlane_u32(pi, static_cast<int>(j));
                     w += static_cast<uint32_t>(mk >> lane) & 1u;
+                };
+                if (je - j0 == static_cast<uint32_t>(kRecChunkL)) {
+#pragma unroll
+                    for (int u = 0; u < kRecChunkL; ++u) append(j0 + u);
+                } else {
+                    for (uint32_t j = j0; j < je; ++j) append(j);
                 }
                 nb = static_cast<uint32_t>(w - myrow);
             }
