@@ -496,9 +496,8 @@ struct RadLds {
 
 struct FillLds : RadLds {
     uint8_t rows[kWave * (kRowCap + 1)];   // per-query output staging: staged-point slots
-    uint64_t fpos[kWave];                  // rows being flushed: global position
-    uint8_t flim[kWave];                   // and the entries that fit the row's slot
-    uint8_t flist[kWave];                  // lanes whose rows are flushed
+    uint64_t fpos[kWave];                  // rows being flushed, by list entry: global position
+    uint32_t fmeta[kWave];                 // and lane | entries that fit the row's slot << 8
 };
 
 // the range form also keeps the candidates' ends and records the candidate
@@ -1167,16 +1166,18 @@ __device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a
         if (!fm) return;
         const int nf = __popcll(fm);
         if (go) {
-            L.fpos[lane] = gpos;
-            L.flim[lane] = static_cast<uint8_t>(left < nb ? left : nb);
-            L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+            const uint32_t i = rank_below(fm);
+            L.fpos[i] = gpos;
+            L.fmeta[i] = static_cast<uint32_t>(lane) | (static_cast<uint32_t>(left < nb ? left : nb) << 8);
         }
         wave_sync();
         for (int i0 = 0; i0 < nf; i0 += 2) {
             const int i = i0 + half;
             if (i < nf) {
-                const int l = L.flist[i];
-                if (hl < L.flim[l]) out[L.fpos[l] + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+                const uint32_t meta = L.fmeta[i];
+                const uint64_t pos = L.fpos[i];
+                const uint32_t slot = L.rows[(meta & 0xFFu) * (kRowCap + 1) + hl];  // hl < kRowCap + 1
+                if (static_cast<uint32_t>(hl) < (meta >> 8)) out[pos + hl] = __float_as_uint(L.pts[slot].w);
             }
         }
         if (go) {
@@ -1277,15 +1278,16 @@ __device__ __forceinline__ void struct_body(StructLds &L, const SearchArgs &a, c
             const int nf = __popcll(fm);
             if (go) {
                 const uint64_t room = gend > gpos ? gend - gpos : 0ull;
-                L.fpos[lane] = gpos;
-                L.flim[lane] = static_cast<uint8_t>(room < nb ? room : nb);
-                L.flist[rank_below(fm)] = static_cast<uint8_t>(lane);
+                const uint32_t i = rank_below(fm);
+                L.fpos[i] = gpos;
+                L.fmeta[i] = static_cast<uint32_t>(lane) | (static_cast<uint32_t>(room < nb ? room : nb) << 8);
             }
             wave_sync();
             for (int i = half; i < nf; i += 2) {
-                const int l = L.flist[i];
-                if (hl < L.flim[l])
-                    a.indices[L.fpos[l] + hl] = __float_as_uint(L.pts[L.rows[l * (kRowCap + 1) + hl]].w);
+                const uint32_t meta = L.fmeta[i];
+                const uint64_t pos = L.fpos[i];
+                const uint32_t slot = L.rows[(meta & 0xFFu) * (kRowCap + 1) + hl];  // hl < kRowCap + 1
+                if (static_cast<uint32_t>(hl) < (meta >> 8)) a.indices[pos + hl] = __float_as_uint(L.pts[slot].w);
             }
             if (go) {
                 gpos += nb;
