@@ -1,5 +1,8 @@
 """Full-size GPU checks on the 10M-point LiDAR tile, in the launch
-configuration the benchmark times (leaf size 16, every point a query).
+configuration the benchmark times (leaf size 64, every point a query, the
+count pass recording the hits and the fill writing rows from the records,
+through the C ABI as the benchmark calls it); the search fill is checked the
+same way on one curve.
 
 The oracle cannot recompute all 10M neighbourhoods in seconds, so sampled
 rows are compared element by element and the rest is checked through
@@ -17,8 +20,38 @@ from tests._parity import announce
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 N = 10_000_000
-LEAF = 16
+LEAF = 64
 SAMPLE = 1500
+
+
+def _count_fill(tree, kernel, r, record):
+    """Count call, then fill call into a buffer pre-set to -1, on one
+    workspace and the current stream (the benchmark's two calls)."""
+    import ctypes
+
+    import torch
+
+    import paper_2603_06771_amd as sfc
+    from paper_2603_06771_amd import _binding as B
+    L = B.load()
+    counts = torch.empty(N, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+    base = (ctypes.byref(tree.view), None, N, sfc.KERNELS[kernel], float(r),
+            ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(offsets.data_ptr()))
+    flags = B.RECORD_HITS if record else 0
+    need = ctypes.c_size_t(0)
+    B.check(L.radius_search(*base, None, 0, flags, None, ctypes.byref(need), None), "size")
+    ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    B.check(L.radius_search(*base, None, 0, flags, ctypes.c_void_p(ws.data_ptr()), ctypes.byref(need), stream),
+            "count")
+    total = int(offsets[-1].item())
+    idx = torch.full((total,), -1, dtype=torch.int32, device="cuda")
+    B.check(L.radius_search(*base, ctypes.c_void_p(idx.data_ptr()), total, B.REUSE_COUNTS | flags,
+                            ctypes.c_void_p(ws.data_ptr()), ctypes.byref(need), stream), "fill")
+    torch.cuda.synchronize()
+    del ws
+    return counts, offsets, idx, total
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +65,8 @@ def dev(cloud):
     return torch.from_numpy(cloud).cuda()
 
 
-@pytest.mark.parametrize("curve", ["hilbert", "morton"])
-def test_radius_fullsize_sampled(cloud, dev, curve):
-    import torch
-
+@pytest.mark.parametrize("curve,record", [("hilbert", True), ("morton", True), ("hilbert", False)])
+def test_radius_fullsize_sampled(cloud, dev, curve, record):
     import paper_2603_06771_amd as sfc
     tree = sfc.build_linear_octree(dev, curve, 21, LEAF)
     perm = tree.perm().cpu().numpy().view(np.uint32)
@@ -44,12 +75,8 @@ def test_radius_fullsize_sampled(cloud, dev, curve):
     for r in (0.5, 3.0):
         grid = oracle.Grid(cloud, r, 3)
         for kernel in ("sphere", "cube"):
-            announce(f"fullsize {curve} {kernel} r={r}")
-            counts, offsets = sfc.radius_count(tree, None, kernel, r)
-            total = int(offsets[-1].item())
-            idx = torch.full((total,), -1, dtype=torch.int32, device="cuda")
-            sfc.radius_fill(tree, counts, offsets, idx, None, kernel, r)
-            torch.cuda.synchronize()
+            announce(f"fullsize {curve} {kernel} r={r} record={record}")
+            counts, offsets, idx, total = _count_fill(tree, kernel, r, record)
             if r == 3.0:
                 assert total > 2 ** 31  # 64-bit offsets in use
             # every slot written, every row holds its own centre
