@@ -88,6 +88,15 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
            static_cast<uint64_t>(readlane_u32(static_cast<uint32_t>(v), l));
 }
 
+// v_writelane: lane l (wave-uniform) of `old` takes the wave-uniform value v,
+// the other lanes keep theirs.  The compiler has the intrinsic but no builtin
+// for it, so it is bound by its LLVM name (the compiler still schedules it
+// and resolves its hazards; no inline assembly).
+__device__ int sfc_llvm_writelane_i32(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ uint32_t writelane_u32(uint32_t v, int l, uint32_t old) {
+    return static_cast<uint32_t>(sfc_llvm_writelane_i32(static_cast<int>(v), l, static_cast<int>(old)));
+}
+
 __device__ __forceinline__ float wave_min(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
     return v;

@@ -813,9 +813,9 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                     const bool h = point_hit<KERNEL>(L.pts[u], qx, qy, qz, r, r2);
                     cnt += h ? 1u : 0u;
                     const uint64_t m = ballot(h);
-                    const bool mine = static_cast<uint32_t>(lane) == u - t0;
-                    mlo = mine ? static_cast<uint32_t>(m) : mlo;
-                    mhi = mine ? static_cast<uint32_t>(m >> 32) : mhi;
+                    const int at = static_cast<int>(u - t0);
+                    mlo = writelane_u32(static_cast<uint32_t>(m), at, mlo);
+                    mhi = writelane_u32(static_cast<uint32_t>(m >> 32), at, mhi);
                 };
                 for (; t + 4 <= te; t += 4) {
                     test(t);
