@@ -877,9 +877,9 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
 // record, every lane whose bit is set appends the record to its LDS row.
 // No traversal and no distance test.  Two forms, chosen per group by the
 // count pass from the group's mean row length:
-//  - short rows: rows hold one-byte slots into the current chunk of 64
-//    records and are written out (two rows per step, one per half wave) once
-//    they could overflow and after every chunk;
+//  - short rows: rows hold one-byte slots into the current batch of up to
+//    256 records and are written out (two rows per step, one per half wave)
+//    once they could overflow and after every batch;
 //  - long rows: rows hold indices and outlive chunks; a row is written out
 //    up to the next 128-byte boundary of its output once it reaches it, so
 //    every store but a row's first and last is one whole aligned line.
@@ -887,7 +887,7 @@ constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written p
 constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
 constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
 constexpr int kRecBatch = SFC_REC_BATCH;         // chunks of 64 records loaded per round trip
-static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 8 && kRecLine <= 32 &&
+static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 4 && kRecLine <= 32 &&
                   (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
               "record fill shapes");
 
@@ -898,7 +898,7 @@ struct RecLds {
     uint8_t rows[kWave * (kRowCap + 1)];
     uint64_t fpos[kWave];   // by list entry: output position
     uint32_t fmeta[kWave];  // by list entry: lane | entries to write << 8
-    uint32_t pidx[kWave];   // original indices of the chunk's records
+    uint32_t pidx[kRecBatch * kWave];  // original indices of the batch's records (slot = position in the batch)
 };
 
 __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs &a, const SearchCloud &C,
@@ -958,12 +958,14 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
             blo[u] = static_cast<uint32_t>(pm);
             bhi[u] = static_cast<uint32_t>(pm >> 32);
         }
+        // the previous batch's rows were written (and read) already
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) L.pidx[u * kWave + lane] = bpi[u];
 #pragma unroll
         for (int u = 0; u < kRecBatch; ++u) {
             const uint32_t c0 = b0 + u * kWave;
             if (c0 >= n) break;
             const uint32_t m = min(n - c0, static_cast<uint32_t>(kWave));
-            L.pidx[lane] = bpi[u];  // the previous chunk's rows were written (and read) already
             const uint32_t lo = blo[u], hi = bhi[u];
             for (uint32_t j0 = 0; j0 < m; j0 += kChunk) {
                 flush(kRowCap - kChunk);
@@ -972,19 +974,19 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
                 auto append = [&](uint32_t j) {
                     const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
                                         readlane_u32(lo, static_cast<int>(j));
-                    *w = static_cast<uint8_t>(j);
+                    *w = static_cast<uint8_t>(u * kWave + j);
                     w += static_cast<uint32_t>(mk >> lane) & 1u;
                 };
                 if (je - j0 == static_cast<uint32_t>(kChunk)) {
 #pragma unroll
-                    for (int u = 0; u < kChunk; ++u) append(j0 + u);
+                    for (int v = 0; v < kChunk; ++v) append(j0 + v);
                 } else {
                     for (uint32_t j = j0; j < je; ++j) append(j);
                 }
                 nb = static_cast<uint32_t>(w - myrow);
             }
-            flush(0);  // the rows point into this chunk's records
         }
+        flush(0);  // the rows point into this batch's records
     }
 }
 
