@@ -880,9 +880,10 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
 //  - short rows: rows hold one-byte slots into the current batch of up to
 //    256 records and are written out (two rows per step, one per half wave)
 //    once they could overflow and after every batch;
-//  - long rows: rows hold indices and outlive chunks; a row is written out
-//    up to the next 128-byte boundary of its output once it reaches it, so
-//    every store but a row's first and last is one whole aligned line.
+//  - long rows: rows outlive chunks and batches (slots into a ring of the
+//    last 256 records); a row is written out up to the next 128-byte boundary
+//    of its output once it reaches it, so every store but a row's first and
+//    last (and rare forced ones) is one whole aligned line.
 constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written per aligned run
 constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
 constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
@@ -990,8 +991,16 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
     }
 }
 
+// Long rows hold one-byte slots into a ring of the last 256 records (two
+// batches of 128): before a batch overwrites its half of the ring, rows whose
+// oldest entry lies there are written out whole (rows are first-in
+// first-out, so the oldest entry decides).
+constexpr int kRingHalf = 2 * kWave;  // records per long-row batch
+static_assert(2 * kRingHalf == 256, "ring slots are one byte");
+
 struct RecLdsLong {
-    uint32_t rows[kWave * (kRecRowL + 1)];  // odd stride: appends at different lengths spread over banks
+    uint8_t rows[kWave * (kRecRowL + 1)];  // slots into ring; odd stride spreads the append cursors
+    uint32_t ring[2 * kRingHalf];          // original indices: record position mod 256
     uint64_t fpos[kWave];   // by list entry: output position
     uint32_t fmeta[kWave];  // by list entry: lane | written << 8 | taken off << 16 | left << 24
 };
@@ -1010,15 +1019,13 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
     const uint64_t gend = q.valid ? o1 : 0ull;
     uint64_t left = gend > gpos ? gend - gpos : 0ull;
     uint32_t nb = 0;
-    uint32_t *myrow = L.rows + lane * kStride;
+    uint8_t *myrow = L.rows + lane * kStride;
     uint32_t *out = a.indices;
     const int half = lane >> 5, hl = lane & 31;
-    // all: write every entry; else only rows that reach their next line
-    // boundary, up to it.  Kept entries move to the row's start in the same
-    // step (each lane reads its entry before any lane writes).
-    auto flush = [&](bool all) {
-        const uint32_t to_line = kRecLine - static_cast<uint32_t>(gpos & (kRecLine - 1));
-        const uint32_t drop = all ? nb : (nb >= to_line ? to_line : 0u);
+    // Takes `drop` (at most kRecLine, per lane) entries off the front of each
+    // row and writes them out; the kept entries move to the row's start in the
+    // same step (each lane reads its entry before any lane writes).
+    auto flush = [&](uint32_t drop) {
         const bool go = drop > 0;
         const uint64_t fm = ballot(go);
         if (!fm) return;
@@ -1035,12 +1042,12 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
             if (i < nf) {
                 const uint32_t meta = L.fmeta[i];
                 const uint64_t pos = L.fpos[i];
-                uint32_t *rw = L.rows + (meta & 0xFFu) * kStride;
+                uint8_t *rw = L.rows + (meta & 0xFFu) * kStride;
                 const uint32_t cnt = (meta >> 8) & 0xFFu, drop_l = (meta >> 16) & 0xFFu, rem = meta >> 24;
                 // both reads stay inside the row (hl < kRecLine < kStride; drop + hl clamped)
-                const uint32_t v = rw[hl];
-                const uint32_t keep = rw[min(drop_l + static_cast<uint32_t>(hl), static_cast<uint32_t>(kStride - 1))];
-                if (static_cast<uint32_t>(hl) < cnt) out[pos + hl] = v;
+                const uint32_t slot = rw[hl];
+                const uint8_t keep = rw[min(drop_l + static_cast<uint32_t>(hl), static_cast<uint32_t>(kStride - 1))];
+                if (static_cast<uint32_t>(hl) < cnt) out[pos + hl] = L.ring[slot];
                 if (static_cast<uint32_t>(hl) < rem) rw[hl] = keep;
             }
         }
@@ -1051,38 +1058,54 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
         }
         wave_sync();
     };
+    // entries up to the row's next line boundary, once it holds them
+    auto to_boundary = [&]() {
+        const uint32_t to_line = kRecLine - static_cast<uint32_t>(gpos & (kRecLine - 1));
+        return nb >= to_line ? to_line : 0u;
+    };
     const uint32_t *ridx = a.rec_idx + gg * kRecCap;
     const uint64_t *rmask = a.rec_mask + gg * kRecCap;
-    for (uint32_t b0 = 0; b0 < n; b0 += kRecBatch * kWave) {
-        uint32_t bpi[kRecBatch], blo[kRecBatch], bhi[kRecBatch];
+    uint32_t k = 0;  // batch number
+    for (uint32_t b0 = 0; b0 < n; b0 += kRingHalf, ++k) {
+        constexpr int kPer = kRingHalf / kWave;
+        uint32_t bpi[kPer], blo[kPer], bhi[kPer];
 #pragma unroll
-        for (int u = 0; u < kRecBatch; ++u) {
-            const uint32_t k = b0 + u * kWave + lane;
-            const bool have = k < n;
-            const uint64_t pm = have ? rmask[k] : 0ull;
-            bpi[u] = have ? ridx[k] : 0u;
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t r = b0 + u * kWave + lane;
+            const bool have = r < n;
+            const uint64_t pm = have ? rmask[r] : 0ull;
+            bpi[u] = have ? ridx[r] : 0u;
             blo[u] = static_cast<uint32_t>(pm);
             bhi[u] = static_cast<uint32_t>(pm >> 32);
         }
+        const uint32_t h = k & 1u;  // ring half this batch takes
+        if (k >= 2) {
+            flush(to_boundary());  // afterwards every row holds fewer than kRecLine entries
+            // the half still holds batch k - 2: rows starting there are written out whole
+            flush(nb > 0 && (static_cast<uint32_t>(myrow[0]) >> 7) == h ? nb : 0u);
+        }
 #pragma unroll
-        for (int u = 0; u < kRecBatch; ++u) {
+        for (int u = 0; u < kPer; ++u) L.ring[h * kRingHalf + u * kWave + lane] = bpi[u];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
             const uint32_t c0 = b0 + u * kWave;
             if (c0 >= n) break;
             const uint32_t m = min(n - c0, static_cast<uint32_t>(kWave));
-            const uint32_t pi = bpi[u], lo = blo[u], hi = bhi[u];
+            const uint32_t lo = blo[u], hi = bhi[u];
+            const uint32_t base = h * kRingHalf + u * kWave;
             for (uint32_t j0 = 0; j0 < m; j0 += kRecChunkL) {
-                flush(false);  // afterwards nb < kRecLine, so the chunk fits
+                flush(to_boundary());  // afterwards nb < kRecLine, so the chunk fits
                 const uint32_t je = min(m, j0 + kRecChunkL);
-                uint32_t *w = myrow + nb;
+                uint8_t *w = myrow + nb;
                 auto append = [&](uint32_t j) {
                     const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
                                         readlane_u32(lo, static_cast<int>(j));
-                    *w = readlane_u32(pi, static_cast<int>(j));
+                    *w = static_cast<uint8_t>(base + j);
                     w += static_cast<uint32_t>(mk >> lane) & 1u;
                 };
                 if (je - j0 == static_cast<uint32_t>(kRecChunkL)) {
 #pragma unroll
-                    for (int u = 0; u < kRecChunkL; ++u) append(j0 + u);
+                    for (int v = 0; v < kRecChunkL; ++v) append(j0 + v);
                 } else {
                     for (uint32_t j = j0; j < je; ++j) append(j);
                 }
@@ -1090,8 +1113,8 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
             }
         }
     }
-    flush(false);  // a row may hold up to kRecRowL entries; afterwards fewer than kRecLine,
-    flush(true);   // which one half wave writes
+    flush(to_boundary());  // a row may hold up to kRecRowL entries; afterwards fewer than kRecLine,
+    flush(nb);             // which one half wave writes
 }
 
 // One query's row [pos, end): contained candidates are copied from the
