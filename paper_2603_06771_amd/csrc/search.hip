@@ -888,7 +888,7 @@ constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written p
 constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
 constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
 constexpr int kRecBatch = SFC_REC_BATCH;         // chunks of 64 records loaded per round trip
-static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 4 && kRecLine <= 32 &&
+static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 4 && kRecLine <= 64 &&
                   (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
               "record fill shapes");
 
@@ -1021,7 +1021,9 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
     uint32_t nb = 0;
     uint8_t *myrow = L.rows + lane * kStride;
     uint32_t *out = a.indices;
-    const int half = lane >> 5, hl = lane & 31;
+    // kWave / kRecLine rows per step, lane e of a row's part writes its entry e
+    constexpr int kPerStep = kWave / kRecLine;
+    const int sub = lane / kRecLine, e = lane % kRecLine;
     // Takes `drop` (at most kRecLine, per lane) entries off the front of each
     // row and writes them out; the kept entries move to the row's start in the
     // same step (each lane reads its entry before any lane writes).
@@ -1037,18 +1039,18 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
                          (drop << 16) | ((nb - drop) << 24);
         }
         wave_sync();
-        for (int i0 = 0; i0 < nf; i0 += 2) {
-            const int i = i0 + half;
+        for (int i0 = 0; i0 < nf; i0 += kPerStep) {
+            const int i = i0 + sub;
             if (i < nf) {
                 const uint32_t meta = L.fmeta[i];
                 const uint64_t pos = L.fpos[i];
                 uint8_t *rw = L.rows + (meta & 0xFFu) * kStride;
                 const uint32_t cnt = (meta >> 8) & 0xFFu, drop_l = (meta >> 16) & 0xFFu, rem = meta >> 24;
-                // both reads stay inside the row (hl < kRecLine < kStride; drop + hl clamped)
-                const uint32_t slot = rw[hl];
-                const uint8_t keep = rw[min(drop_l + static_cast<uint32_t>(hl), static_cast<uint32_t>(kStride - 1))];
-                if (static_cast<uint32_t>(hl) < cnt) out[pos + hl] = L.ring[slot];
-                if (static_cast<uint32_t>(hl) < rem) rw[hl] = keep;
+                // both reads stay inside the row (e < kRecLine < kStride; drop + e clamped)
+                const uint32_t slot = rw[e];
+                const uint8_t keep = rw[min(drop_l + static_cast<uint32_t>(e), static_cast<uint32_t>(kStride - 1))];
+                if (static_cast<uint32_t>(e) < cnt) out[pos + e] = L.ring[slot];
+                if (static_cast<uint32_t>(e) < rem) rw[e] = keep;
             }
         }
         if (go) {
@@ -1114,7 +1116,7 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
         }
     }
     flush(to_boundary());  // a row may hold up to kRecRowL entries; afterwards fewer than kRecLine,
-    flush(nb);             // which one half wave writes
+    flush(nb);             // which one step writes
 }
 
 // One query's row [pos, end): contained candidates are copied from the
