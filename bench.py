@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-record", action="store_true",
                     help="radius: the fill searches again instead of writing rows from the hits the count "
                          "pass recorded (SFC_RECORD_HITS, the default)")
+    ap.add_argument("--record-batched", action="store_true",
+                    help="batched: fill from recorded hits (slower on this mix: dense clouds overflow the records "
+                         "and their contained nodes are tested point by point)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--workload", default="radius", choices=["radius", "batched", "served", "subset"],
@@ -129,7 +132,8 @@ def bench_batched(args):
                               cache_path=os.path.join(tempfile.gettempdir(), "sfcoct_bench_autotune.json"), log=log)
     leaves = tune["leaf"]
 
-    plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii)
+    record = bool(args.record_batched)
+    plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii, record=record)
     total = plan.total()
     log(f"[bench] batched plan: {total} neighbours ({total * 4 / 1e9:.2f} GB)")
 
@@ -175,8 +179,8 @@ def bench_batched(args):
 
     # baseline: one launch sequence per cloud
     starts = np.concatenate([[0], np.cumsum(sizes)])
-    singles = [BatchPlan(xyz[starts[c]:starts[c + 1]], [sizes[c]], "hilbert", 21, leaves[c], kernels[c], radii[c])
-               for c in range(len(sizes))]
+    singles = [BatchPlan(xyz[starts[c]:starts[c + 1]], [sizes[c]], "hilbert", 21, leaves[c], kernels[c], radii[c],
+                         record=record) for c in range(len(sizes))]
 
     def per_cloud():
         for p in singles:
@@ -198,7 +202,8 @@ def bench_batched(args):
     base_graph_wall, base_graph_gpu = timed(g.replay, args.steps)
     log(f"[bench] per-cloud eager {base_wall:.2f} ms, graph {base_graph_wall:.2f} ms per step; counts equal: {same}")
 
-    fill_bytes = 16 * n + 8 * (n + 1) + 4 * total
+    # the fill stage's algorithmic bytes (the search fill also reads every point)
+    fill_bytes = 8 * (n + 1) + 4 * total if record else 16 * n + 8 * (n + 1) + 4 * total
     out = {
         "metric": "batched build + radius-search queries/s (256 clouds, one HIP graph)",
         "value": n / (graph_wall / 1e3),
@@ -213,7 +218,8 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batch256_mix_build_radius", "clouds": len(sizes), "points": n,
-                   "neighbours": total, "curve": "hilbert", "leaf": "autotuned per mu group"},
+                   "neighbours": total, "curve": "hilbert", "leaf": "autotuned per mu group",
+                   "record_hits": record},
         "batched": {"graph_ms": round(graph_wall, 3), "graph_gpu_ms": round(graph_gpu, 3),
                     "eager_ms": round(eager_wall, 3), "eager_gpu_ms": round(eager_gpu, 3), "stages_ms": stage_ms},
         "one_launch_sequence_per_cloud": {"eager_ms": round(base_wall, 3), "eager_gpu_ms": round(base_gpu, 3),
@@ -221,7 +227,8 @@ def bench_batched(args):
                                           "graph_gpu_ms": round(base_graph_gpu, 3), "counts_equal": same},
         "speedup_vs_per_cloud": {"eager": base_wall / eager_wall, "graph": base_graph_wall / graph_wall,
                                  "graph_vs_per_cloud_eager": base_wall / graph_wall},
-        "roofline": {"bound": "hbm", "kernel": "k_radius_fill", "achieved": fill_bytes / stage_ms["fill"] / 1e6,
+        "roofline": {"bound": "hbm", "kernel": FILL_STAGE if record else "k_radius_fill",
+                     "achieved": fill_bytes / stage_ms["fill"] / 1e6,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_bytes / stage_ms["fill"] / 1e6 / HBM_PEAK_GBS,
                      "traffic": None},
         "autotune": {"table_ms": tune["table"], "mu_edges": tune["edges"], "cached": tune["cached"],

@@ -835,6 +835,10 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
             }
         };
         uint32_t staged = 0;  // points staged and not yet swept, across candidate batches
+        // Once the records overflow the group is left to the search fill, so
+        // the rest of the walk counts as the plain count does (contained
+        // nodes from their sizes); points already staged are tested either way.
+        auto recording = [&]() { return REC && nrec <= static_cast<uint32_t>(kRecCap); };
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
             for (int c0 = 0; c0 < ncand; c0 += kWave) {
@@ -842,7 +846,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
                 uint64_t mixed, touched, full;
                 const uint32_t len =
                     classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
-                if constexpr (REC) {
+                if (recording()) {
                     if (!touched) continue;
                     stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, body_rec, &staged);
                 } else {
@@ -857,7 +861,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
         traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
         if (staged) {
             wave_sync();
-            if constexpr (REC)
+            if (recording())
                 body_rec(staged);
             else
                 body(staged);

@@ -23,8 +23,11 @@ class BatchPlan:
     points are its queries."""
 
     def __init__(self, xyz, sizes, curve="hilbert", bits=21, leaf_size=32, kernel="sphere", r=1.0, k=None,
-                 capacity: int | None = None):
+                 capacity: int | None = None, record: bool = False):
         torch = _torch()
+        # record: the count pass records every group's hits and the fill
+        # writes the rows from them (SFC_RECORD_HITS; larger workspace)
+        self.flags = B.RECORD_HITS if (record and k is None) else 0
         self.L = B.load()
         self.xyz = _xyz(torch, xyz)
         self.sizes = [int(x) for x in sizes]
@@ -74,7 +77,8 @@ class BatchPlan:
             self.counts = torch.empty(self.n, dtype=torch.int32, device="cuda")
             self.offsets = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
             B.check(self.L.radius_search_batched(nb, cl, None, self.n, _ptr(self.counts), _ptr(self.offsets), None,
-                                                 0, 0, None, ctypes.byref(need), None), "radius_search_batched(size)")
+                                                 0, self.flags, None, ctypes.byref(need), None),
+                    "radius_search_batched(size)")
         self.search_ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
         self.search_need = ctypes.c_size_t(need.value)
         self.indices = None
@@ -106,12 +110,12 @@ class BatchPlan:
             return
         head = (self.B, self.clouds, None, self.n, _ptr(self.counts), _ptr(self.offsets))
         if count:
-            B.check(self.L.radius_search_batched(*head, None, 0, 0, _ptr(self.search_ws),
+            B.check(self.L.radius_search_batched(*head, None, 0, self.flags, _ptr(self.search_ws),
                                                  ctypes.byref(self.search_need), s), "radius_search_batched(count)")
         if fill and self.indices is not None:
-            B.check(self.L.radius_search_batched(*head, _ptr(self.indices), self.capacity, B.REUSE_COUNTS,
-                                                 _ptr(self.search_ws), ctypes.byref(self.search_need), s),
-                    "radius_search_batched(fill)")
+            B.check(self.L.radius_search_batched(*head, _ptr(self.indices), self.capacity,
+                                                 B.REUSE_COUNTS | self.flags, _ptr(self.search_ws),
+                                                 ctypes.byref(self.search_need), s), "radius_search_batched(fill)")
 
     def run(self):
         """One step: build every tree, then search (launches only)."""

@@ -29,13 +29,14 @@ def _csr(plan):
     return plan.counts.cpu().numpy(), plan.offsets.cpu().numpy(), plan.indices.cpu().numpy()
 
 
-def test_radius_plan_graph_replays(tmp_path):
+@pytest.mark.parametrize("record", [False, True])
+def test_radius_plan_graph_replays(tmp_path, record):
     import torch
     from paper_2603_06771_amd.plan import BatchPlan
     clouds = _clouds()
     xyz = _dev(np.concatenate(clouds))
-    announce("radius plan: eager")
-    plan = BatchPlan(xyz, SIZES, "hilbert", 21, LEAF, KERN, RADII)
+    announce(f"radius plan: eager (record={record})")
+    plan = BatchPlan(xyz, SIZES, "hilbert", 21, LEAF, KERN, RADII, record=record)
     plan.run()
     torch.cuda.synchronize()
     c, o, i = _csr(plan)
