@@ -869,7 +869,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
     }
     if (q.valid) a.counts[row] = cnt;
     if constexpr (REC) {
-        // rows averaging a line or more take the long-row form
+        // groups whose rows average kRecLongMean entries or more take the long-row form
         const uint32_t hits = __shfl(wave_inclusive_sum(q.valid ? cnt : 0u), kWave - 1);
         const uint32_t nvalid = static_cast<uint32_t>(__popcll(ballot(q.valid)));
         const uint32_t form = hits >= kRecLongMean * nvalid ? kRecLongRows : 0u;
@@ -891,7 +891,7 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
 constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written per aligned run
 constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
 constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
-constexpr int kRecBatch = SFC_REC_BATCH;         // chunks of 64 records loaded per round trip
+constexpr int kRecBatch = SFC_REC_BATCH;         // short rows: chunks of 64 records per load round trip and slot table
 static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 4 && kRecLine <= 64 &&
                   (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
               "record fill shapes");
