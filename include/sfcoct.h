@@ -163,8 +163,10 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
  *             one of them (its index and the mask of those queries), and
  *             the fill writes the rows from these records instead of
  *             searching again; a group whose records do not fit (more than
- *             4096) is filled by the search.  The workspace grows by about
- *             48 KB per 64 queries.  With SFC_REUSE_COUNTS the
+ *             4096), and a group of far-apart external queries (served one
+ *             query per wave), is filled by the search.  Rows come out in
+ *             the same order as without the bit.  The workspace grows by
+ *             about 48 KB per 64 queries.  With SFC_REUSE_COUNTS the
  *             records of the preceding count call on the same workspace are
  *             used, so both calls must pass this bit, the same workspace and
  *             identical arguments.  The result is the same with or without it.
