@@ -12,13 +12,17 @@ the timed region; the output buffer is sized once (capacity protocol), so no
 host synchronisation happens inside a step.  --no-record times the search
 fill instead (the same result).
 
-Prints ONE JSON line (see the keys below).  The fill stage's achieved
-bandwidth is measured with events on the launch stream around every fill
-stage; its algorithmic bytes are
-  8 B x (queries + 1) (row offsets read) + 4 B x neighbours (indices written)
-and, for the search fill, also 16 B x queries (points read once) + 36 B x
-nodes (tree read once).
-The CPU baseline is the oracle (uniform-grid search) on a bounded sample.
+Prints ONE JSON line.  `roofline` is that of whole radius_search calls
+(count pass + scan + fill stage, event-timed on the launch stream), with
+algorithmic bytes per call
+  (16 + 4 + 8) B x queries (point read, count and row offset written)
+  + 4 B x neighbours (indices written) + 36 B x nodes (tree read once);
+`fill_stage` keeps the fill stage alone (row offsets read, indices written).
+After the timed steps (outside them): `knn` (k = 8, 16, 32 on the same tile,
+16 + 8k B per query), `c1` (the 100k-point uniform configuration), the CPU
+baseline (the oracle on a bounded sample, and on one thread for the 100k
+configuration) and `served` (64 resident clouds, Poisson requests, p50/p99
+latency at 95 % of the continuous-batching capacity).
 """
 from __future__ import annotations
 
@@ -37,6 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the fill stage of a recorded-hits search: the two record-writing forms and
 # the search fill for groups whose records did not fit
 FILL_STAGE = "k_radius_fill_rec + k_radius_fill_rec_long + k_radius_fill"
+# one radius_search call: count pass, scan of the counts, fill stage
+SEARCH = "radius_search: k_radius_count_rec + k_scan_* + " + FILL_STAGE
+SEARCH_NO_RECORD = "radius_search: k_radius_count + k_scan_* + k_radius_fill"
+KNN_K = (8, 16, 32)
 CURVES = ("morton", "hilbert")
 KERNELS = ("sphere", "cube")
 RADII = (0.5, 1.0, 2.0, 3.0)
@@ -51,6 +59,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=100_000, help="queries per (kernel, r) for the oracle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-knn", action="store_true", help="radius: skip the k-NN leg")
+    ap.add_argument("--no-served", action="store_true", help="radius: skip the served leg")
     ap.add_argument("--no-record", action="store_true",
                     help="radius: the fill searches again instead of writing rows from the hits the count "
                          "pass recorded (SFC_RECORD_HITS, the default)")
@@ -243,7 +253,7 @@ def _gen_served_cloud(args):
     return datagen.lidar_tile(n, seed=seed)
 
 
-def bench_served(args):
+def served_measure(args, n_requests: int):
     """64 resident LiDAR clouds (3.5M..9M points each, Hilbert octrees in HBM);
     a Poisson stream of requests, each naming a cloud, 1e3..1e6 of its points
     as queries and a radius search (kernel, r ~ U(0.5, 3)) or a k-NN search
@@ -279,7 +289,7 @@ def bench_served(args):
     log(f"[bench] {len(sizes)} resident clouds, {n_points} points, {res.used / 1e9:.1f} GB; generated + built in "
         f"{time.perf_counter() - t0:.1f} s (builds {build_s:.2f} s)")
 
-    base = datagen.request_stream(args.requests, len(sizes), sizes, rate_per_s=1.0)
+    base = datagen.request_stream(n_requests, len(sizes), sizes, rate_per_s=1.0)
     log(f"[bench] {len(base)} requests, {sum(len(d['rows']) for d in base)} queries")
 
     def requests(rate):
@@ -317,30 +327,36 @@ def bench_served(args):
             loads[str(frac)][m] = summary(st)
             log(f"[bench] load {frac:.2f} ({rate:.0f} req/s) {m}: p50 {loads[str(frac)][m]['p50_ms']:.2f} ms, "
                 f"p99 {loads[str(frac)][m]['p99_ms']:.2f} ms")
-    at95 = loads["0.95"]
-    out = {
+    out = {"clouds": len(sizes), "points": n_points, "requests": n_requests, "slots": 3,
+           "max_batch_requests": 64, "capacity": cap, "loads": loads, "resident_gb": res.used / 1e9,
+           "build_s": build_s}
+    del srv, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def served_line(args, sv):
+    """The JSON line of --workload served."""
+    at95 = sv["loads"]["0.95"]["continuous"]
+    return {
         "metric": "served p50/p99 latency at 95% of capacity (continuous batching), queries/s",
-        "value": at95["continuous"]["queries_per_s"],
+        "value": at95["queries_per_s"],
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": args.requests,
+        "steps": sv["requests"],
         "warmup": 64,
-        "ms_per_step": at95["continuous"]["mean_ms"],
+        "ms_per_step": at95["mean_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "served64_lidar_poisson", "clouds": len(sizes), "points": n_points,
-                   "requests": args.requests, "slots": 3, "max_batch_requests": 64},
-        "p50_ms": at95["continuous"]["p50_ms"],
-        "p99_ms": at95["continuous"]["p99_ms"],
-        "capacity": cap,
-        "loads": loads,
-        "resident_gb": res.used / 1e9,
-        "build_s": build_s,
+        "config": {"workload": "served64_lidar_poisson", "clouds": sv["clouds"], "points": sv["points"],
+                   "requests": sv["requests"], "slots": sv["slots"], "max_batch_requests": sv["max_batch_requests"]},
+        "p50_ms": at95["p50_ms"],
+        "p99_ms": at95["p99_ms"],
+        **{k: sv[k] for k in ("capacity", "loads", "resident_gb", "build_s")},
     }
-    print(json.dumps(out), flush=True)
 
 
 def bench_subset(args):
@@ -370,7 +386,7 @@ def bench_subset(args):
                 for _ in range(args.warmup + args.steps):
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     a.record()
-                    sfc.radius_search(t, q, k, r, capacity=cap)
+                    sfc.radius_search(t, q, k, r, capacity=cap, check=False)
                     b.record()
                     b.synchronize()
                     ts.append(a.elapsed_time(b))
@@ -388,6 +404,109 @@ def bench_subset(args):
     print(json.dumps(res), flush=True)
 
 
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM bandwidth beside the nominal peak: a plain device copy
+    of nbytes (bytes read + bytes written over the event-timed copy), GB/s."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2.0 * nbytes / ms / 1e6
+
+
+def knn_leg(torch, sfc, B, L, xyz, n: int, leaf: int, reps: int):
+    """k-NN on the same 10M-point tile: Hilbert tree, every point a query,
+    k = 8, 16, 32 (event-timed calls on the current stream, mean of `reps`
+    after one warm-up).  Algorithmic bytes per query: 16 (the query point) +
+    8k (index and squared distance of each neighbour)."""
+    import ctypes
+
+    import numpy as np
+    tree = sfc.build_linear_octree(xyz, "hilbert", 21, leaf)
+    stream = torch.cuda.current_stream()
+    out = {}
+    tot_b, tot_ms = 0.0, 0.0
+    for k in KNN_K:
+        idx = torch.empty((n, k), dtype=torch.int32, device="cuda")
+        d2 = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        need = ctypes.c_size_t(0)
+        args = (ctypes.byref(tree.view), None, n, k, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()))
+        B.check(L.knn_search(*args, None, ctypes.byref(need), None), "knn_search(size)")
+        ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
+        call = (ctypes.c_void_p(ws.data_ptr()), ctypes.byref(need), ctypes.c_void_p(stream.cuda_stream))
+        B.check(L.knn_search(*args, *call), "knn_search")
+        ev = _events(torch, reps)
+        for a, b in ev:
+            a.record(stream)
+            B.check(L.knn_search(*args, *call), "knn_search")
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        by = (16.0 + 8.0 * k) * n
+        tot_b += by
+        tot_ms += ms
+        out[f"k={k}"] = {"ms": round(ms, 4), "queries_per_s": n / (ms / 1e3),
+                         "frac": by / ms / 1e6 / HBM_PEAK_GBS}
+        del idx, d2, ws
+    del tree
+    torch.cuda.empty_cache()
+    return {"workload": "lidar_tile_10M_knn", "curve": "hilbert", "leaf_size": leaf,
+            "queries_per_s": len(KNN_K) * n / (tot_ms / 1e3), "ms_total": round(tot_ms, 4),
+            "roofline": {"bound": "hbm", "achieved": tot_b / tot_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": tot_b / tot_ms / 1e6 / HBM_PEAK_GBS, "alg_bytes_per_query": "16 + 8k"},
+            "detail": out}
+
+
+def c1_leg(torch, sfc, reps: int = 20):
+    """The 100k-point uniform configuration (Morton, leaf 32, every point a
+    query, sphere r = 0.01): GPU latency of one radius_search (count + fill,
+    median of `reps`), and the oracle on one host thread on the same input."""
+    import numpy as np
+
+    from paper_2603_06771_amd import datagen
+    pts = datagen.uniform(100_000, seed=datagen.SEED_UNIFORM)
+    xyz = torch.from_numpy(pts).cuda()
+    tree = sfc.build_linear_octree(xyz, "morton", 21, 32)
+    c, o, _ = sfc.radius_search(tree, None, "sphere", 0.01)
+    cap = int(o[-1])
+    ts = []
+    for i in range(reps + 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sfc.radius_search(tree, None, "sphere", 0.01, capacity=cap, check=False)
+        b.record()
+        b.synchronize()
+        if i >= 2:
+            ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    return pts, {"workload": "uniform_100k_sphere_r0.01", "gpu_ms": round(ms, 4),
+                 "queries_per_s": pts.shape[0] / (ms / 1e3), "mu": cap / pts.shape[0]}
+
+
+def c1_single_thread(pts):
+    """The oracle on one host thread over the whole 100k-point configuration
+    (grid build + count + fill)."""
+    import oracle
+    t_prev = oracle.get_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.radius_search(pts, pts, "sphere", 0.01)
+        s = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(t_prev)
+    return {"value": pts.shape[0] / s, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {pts.shape[0]} queries of the 100k uniform configuration (grid build + count + fill): "
+                      f"{s:.3f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -398,21 +517,24 @@ def main():
         bench_batched(args)
         return
     if args.workload == "served":
-        bench_served(args)
+        print(json.dumps(served_line(args, served_measure(args, args.requests))), flush=True)
         return
     if args.workload == "subset":
         bench_subset(args)
         return
+    import ctypes
+
     import numpy as np
     import torch
 
     import paper_2603_06771_amd as sfc
+    from paper_2603_06771_amd import _binding as B
     from paper_2603_06771_amd import datagen
 
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.perf_counter()
     pts = datagen.lidar_tile(args.points, seed=datagen.SEED_LIDAR)
-    gen_s = time.perf_counter() - t0
-    print(f"[bench] generated {pts.shape[0]} points in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    log(f"[bench] generated {pts.shape[0]} points in {time.perf_counter() - t0:.1f} s")
     xyz = torch.from_numpy(pts).cuda()
     n = pts.shape[0]
     if args.copy_calib:
@@ -422,6 +544,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()
+    L = B.load()
 
     # size the output once: the largest neighbour total over the workload
     trees = {c: sfc.build_linear_octree(xyz, c, 21, args.leaf) for c in CURVES}
@@ -430,28 +553,21 @@ def main():
     for c in CURVES:
         for k in KERNELS:
             for r in RADII:
-                counts, offsets, _ = sfc.radius_search(trees[c], None, k, r, capacity=0)
+                counts, offsets = sfc.radius_count(trees[c], None, k, r)
                 totals[c, k, r] = int(offsets[-1].item())
                 cap = max(cap, totals[c, k, r])
     infos = {c: trees[c].info() for c in CURVES}
     del trees
     torch.cuda.synchronize()
-    print(f"[bench] output capacity {cap} indices ({cap * 4 / 1e9:.2f} GB)", file=sys.stderr, flush=True)
+    log(f"[bench] output capacity {cap} indices ({cap * 4 / 1e9:.2f} GB)")
 
-    import ctypes
-
-    from paper_2603_06771_amd import _binding as B
-    L = B.load()
     counts = torch.empty(n, dtype=torch.int32, device="cuda")
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
     indices = torch.empty(cap, dtype=torch.int32, device="cuda")
     need = ctypes.c_size_t(0)
     record = not args.no_record
     rf = B.RECORD_HITS if record else 0
-
-    def fill_events():
-        return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(len(CURVES) * len(KERNELS) * len(RADII))]
+    combos = [(c, k, r) for c in CURVES for k in KERNELS for r in RADII]
 
     def step(events=None, build_events=None):
         i = 0
@@ -470,16 +586,18 @@ def main():
                         B.check(L.radius_search(*base, None, 0, rf, None, ctypes.byref(need), None), "size")
                         step.ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
                     ws = ctypes.c_void_p(step.ws.data_ptr())
+                    if events is not None:
+                        events[i][0].record(stream)
                     # count pass + scan
                     B.check(L.radius_search(*base, None, 0, rf, ws, ctypes.byref(need), ctypes.c_void_p(sp)),
                             "radius count")
                     if events is not None:
-                        events[i][0].record(stream)
+                        events[i][1].record(stream)
                     # fill pass only (counts/offsets from the call above)
                     B.check(L.radius_search(*base, ctypes.c_void_p(indices.data_ptr()), cap, B.REUSE_COUNTS | rf,
                                             ws, ctypes.byref(need), ctypes.c_void_p(sp)), "radius fill")
                     if events is not None:
-                        events[i][1].record(stream)
+                        events[i][2].record(stream)
                     i += 1
             del tree
 
@@ -487,62 +605,72 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    ev_fill = [fill_events() for _ in range(args.steps)]
+    ev = [[tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in combos] for _ in range(args.steps)]
     ev_build = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in CURVES]
                 for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step(ev_fill[s], ev_build[s])
+        step(ev[s], ev_build[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
 
-    combos = [(c, k, r) for c in CURVES for k in KERNELS for r in RADII]
-    fill_ms = {cb: [] for cb in combos}
-    for s in range(args.steps):
-        for i, cb in enumerate(combos):
-            a, b = ev_fill[s][i]
-            fill_ms[cb].append(a.elapsed_time(b))
+    count_ms = {cb: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
+                for i, cb in enumerate(combos)}
+    fill_ms = {cb: float(np.mean([ev[s][i][1].elapsed_time(ev[s][i][2]) for s in range(args.steps)]))
+               for i, cb in enumerate(combos)}
     build_ms = {c: float(np.mean([ev_build[s][i][0].elapsed_time(ev_build[s][i][1]) for s in range(args.steps)]))
                 for i, c in enumerate(CURVES)}
 
-    # algorithmic bytes of one fill stage: the row offsets read and the indices
-    # written; the search fill must also read every point and node once
-    def alg_bytes(c, total):
-        if record:
-            return 8 * (n + 1) + 4 * total
-        return 16 * n + 8 * (n + 1) + 4 * total + 36 * infos[c]["n_nodes"]
+    # algorithmic bytes of one radius_search over every point: the query point
+    # read once (16 B), its count (4 B) and row offset (8 B) written, the
+    # indices (4 B per neighbour) and the tree read once (36 B per node: the
+    # 32-B node record and the child link); the fill stage alone: the row
+    # offsets read and the indices written
+    def search_bytes(c, total):
+        return (16 + 4 + 8) * n + 8 + 4 * total + 36 * infos[c]["n_nodes"]
 
-    tot_bytes = 0.0
-    tot_ms = 0.0
+    def fill_bytes(total):
+        return 8 * (n + 1) + 4 * total
+
+    s_bytes = s_ms = f_bytes = f_ms = 0.0
     detail = {}
     for cb in combos:
         c, k, r = cb
-        ms = float(np.mean(fill_ms[cb]))
-        b = alg_bytes(c, totals[cb])
-        tot_bytes += b
-        tot_ms += ms
-        detail[f"{c}/{k}/r={r}"] = {"mu": totals[cb] / n, "fill_ms": round(ms, 4),
-                                    "fill_GBps": round(b / ms / 1e6, 1)}
-    achieved = tot_bytes / tot_ms / 1e6  # GB/s
-    # measured HBM bytes per fill stage (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid only
-    # while the kernel source is the one the counters were taken on
-    traffic = None
-    try:
-        from paper_2603_06771_amd import rocprof_summary
-        name = "radius_fill_stage_record_lidar10M_traffic.json" if record else "k_radius_fill_lidar10M_traffic.json"
-        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
-        src = os.path.join(ROOT, "paper_2603_06771_amd", "csrc", "search.hip")
-        if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 64 and n == 10_000_000:
-            traffic = rec["bytes_per_launch"]
-    except (OSError, ValueError, KeyError):
-        traffic = None
+        sb, fb = search_bytes(c, totals[cb]), fill_bytes(totals[cb])
+        ms = count_ms[cb] + fill_ms[cb]
+        s_bytes += sb
+        s_ms += ms
+        f_bytes += fb
+        f_ms += fill_ms[cb]
+        detail[f"{c}/{k}/r={r}"] = {"mu": totals[cb] / n, "count_ms": round(count_ms[cb], 4),
+                                    "fill_ms": round(fill_ms[cb], 4), "search_ms": round(ms, 4),
+                                    "frac": sb / ms / 1e6 / HBM_PEAK_GBS}
+    achieved = s_bytes / s_ms / 1e6  # GB/s over whole radius_search calls
+    f_achieved = f_bytes / f_ms / 1e6
+
+    def traffic_of(name):
+        """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        copy-calibrated), valid only while the kernel source is the one the
+        counters were taken on."""
+        try:
+            from paper_2603_06771_amd import rocprof_summary
+            rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+            src = os.path.join(ROOT, "paper_2603_06771_amd", "csrc", "search.hip")
+            if rec.get("source_sha") == rocprof_summary.source_sha(src) and args.leaf == 64 and n == 10_000_000:
+                return rec["bytes_per_launch"]
+        except (OSError, ValueError, KeyError):
+            pass
+        return None
+
     queries_per_step = len(combos) * n
     value = queries_per_step / (ms_per_step / 1e3)
+    log(f"[bench] {ms_per_step:.2f} ms per step; radius_search {s_ms / len(combos):.3f} ms per call on average")
+    copy_gbs = copy_bandwidth(torch)
 
     out = {
-        "metric": "radius-search queries/s at 10M pts (+% HBM roofline)",
+        "metric": "radius-search queries/s at 10M pts (+% HBM roofline); served p50/p99 ms",
         "value": value,
         "unit": "queries/s",
         "n_gpus": 1,
@@ -558,10 +686,18 @@ def main():
                    "kernels": list(KERNELS), "radii_m": list(RADII), "leaf_size": args.leaf,
                    "queries_per_step": queries_per_step, "builds_per_step": len(CURVES),
                    "record_hits": record},
-        "roofline": {"bound": "hbm", "kernel": FILL_STAGE if record else "k_radius_fill", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": tot_bytes / len(combos)},
+        "roofline": {"bound": "hbm", "kernel": SEARCH if record else SEARCH_NO_RECORD, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_of("radius_search_record_lidar10M_traffic.json" if record
+                                           else "radius_search_lidar10M_traffic.json"),
+                     "alg_bytes_per_launch": s_bytes / len(combos), "ms_per_launch": s_ms / len(combos),
+                     "alg_bytes_per_query": "16 + 4 + 8 + 4 mu + 36 nodes / n",
+                     "stream_copy_GBps": copy_gbs},
+        "fill_stage": {"kernel": FILL_STAGE if record else "k_radius_fill", "achieved": f_achieved,
+                       "frac": f_achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": f_bytes / len(combos),
+                       "ms_per_launch": f_ms / len(combos),
+                       "traffic": traffic_of("radius_fill_stage_record_lidar10M_traffic.json" if record
+                                             else "k_radius_fill_lidar10M_traffic.json")},
         "build_ms": {c: round(v, 3) for c, v in build_ms.items()},
         # beside the end-to-end value: the searches alone (the step less its
         # event-timed builds) and the build throughput
@@ -572,9 +708,27 @@ def main():
                  for c in CURVES},
         "detail": detail,
     }
+    del indices, counts, offsets
+    step.ws = None
+    torch.cuda.empty_cache()
+    if not args.no_knn:
+        log("[bench] k-NN leg")
+        out["knn"] = knn_leg(torch, sfc, B, L, xyz, n, args.leaf, 3)
+    c1_pts, out["c1"] = c1_leg(torch, sfc)
+    del xyz
+    torch.cuda.empty_cache()
     if not args.no_cpu:
-        print("[bench] timing the oracle on a sample", file=sys.stderr, flush=True)
+        log("[bench] timing the oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(pts, args.cpu_sample)
+        out["cpu_baseline"]["c1_single_thread"] = c1_single_thread(c1_pts)
+    del pts
+    if not args.no_served:
+        log("[bench] served leg")
+        sv = served_measure(args, args.requests)
+        at95 = sv["loads"]["0.95"]["continuous"]
+        out["served"] = {"p50_ms": at95["p50_ms"], "p99_ms": at95["p99_ms"],
+                         "queries_per_s": at95["queries_per_s"], "requests_per_s": at95["requests_per_s"],
+                         "offered_load": 0.95, **sv}
     print(json.dumps(out), flush=True)
 
 

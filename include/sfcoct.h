@@ -40,7 +40,7 @@ typedef enum {
     SFC_OK = 0,
     SFC_EINVAL = -1,      /* bad argument (null pointer, size, enum) */
     SFC_EWORKSPACE = -2,  /* workspace too small or misaligned */
-    SFC_ECAPACITY = -3,   /* reserved: output capacity checks are device-side */
+    SFC_ECAPACITY = -3,   /* radius_search_check: the neighbour total exceeds the capacity */
     SFC_EHIP = -4,        /* a HIP runtime call or kernel launch failed */
     SFC_ENOTSUP = -5      /* valid but unsupported request (e.g. k > 512) */
 } sfc_status;
@@ -168,8 +168,19 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
  *             the same order as without the bit.  The workspace grows by
  *             about 48 KB per 64 queries.  With SFC_REUSE_COUNTS the
  *             records of the preceding count call on the same workspace are
- *             used, so both calls must pass this bit, the same workspace and
- *             identical arguments.  The result is the same with or without it.
+ *             used, so both calls pass this bit, the same workspace and
+ *             identical arguments.  The count stamps the records with a
+ *             number the library gives each count call on a workspace
+ *             address and a hash of the call's arguments; a fill that finds
+ *             another stamp (the count did not record, ran on another
+ *             workspace or with other arguments, or a later count call used
+ *             the workspace) searches instead, so the result is the same
+ *             with or without the bit.
+ *
+ * Capacity protocol: the indices are written only when the neighbour total
+ * offsets[nq] fits `capacity`, which the kernels check on the device (no
+ * host round trip).  The caller learns the outcome at its own sync point
+ * from offsets[nq], or with radius_search_check below.
  */
 #define SFC_REUSE_COUNTS 1u
 #define SFC_NO_PRUNE 2u
@@ -178,6 +189,16 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
 int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
                   uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
                   uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
+
+/* The sync point of the capacity protocol (Section 5.1 output of
+ * neighboursPrune as CSR): waits for `stream`, stores the neighbour total
+ * offsets[nq] (offsets: the device array a radius_search or
+ * radius_search_batched call on that stream wrote) in *total (a host
+ * pointer) and returns SFC_ECAPACITY if it exceeds `capacity` (the indices
+ * were then not written: call again with a buffer of at least *total
+ * entries and SFC_REUSE_COUNTS), SFC_OK otherwise.  This call blocks the
+ * host; it allocates nothing.  SFC_EHIP if the copy or the wait fails. */
+int radius_search_check(const uint64_t *offsets, int64_t nq, uint64_t capacity, uint64_t *total, void *stream);
 
 /* Section 5.1, the neighboursStruct form of radius_search: the same
  * neighbour set per query, split into the ranges of sorted positions of the

@@ -15,12 +15,14 @@ from . import _binding as B
 
 __all__ = ["encode_sfc", "build_linear_octree", "radius_search", "radius_count", "radius_fill", "knn_search", "Octree",
            "Batch", "build_batch", "radius_search_batched", "knn_search_batched", "knn_locality", "choose_curve",
-           "radius_search_struct",
+           "radius_search_struct", "SfcError", "SfcCapacityError",
            "CURVES", "KERNELS", "library_path"]
 
 CURVES = {"morton": B.MORTON, "hilbert": B.HILBERT}
 KERNELS = {"sphere": B.SPHERE, "circle": B.CIRCLE, "cube": B.CUBE, "square": B.SQUARE}
 library_path = B.LIB_PATH
+SfcError = B.SfcError
+SfcCapacityError = B.SfcCapacityError
 
 
 def _torch():
@@ -149,13 +151,17 @@ def build_linear_octree(xyz, curve="morton", bits: int = 21, leaf_size: int = 32
 
 
 def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, capacity: int | None = None,
-                  prune: bool = True, record: bool = False):
+                  prune: bool = True, record: bool = False, check: bool = True):
     """Section 3.2 / 5.1: CSR (counts int32, offsets int64 [nq+1], indices
     int32 original point indices).  queries=None searches around every cloud
     point, rows in sorted (curve) order.  Without a capacity the count pass
-    runs first and the host reads the total before the fill pass.  record:
-    the fill writes rows from the hits the count pass recorded (same
-    result, larger workspace)."""
+    runs first and the host reads the total before the fill pass.  With a
+    capacity both passes run in one call; then the host waits for the result
+    and raises SfcCapacityError (its `total` is the capacity needed) if the
+    indices did not fit, unless check=False (no host wait: the caller
+    compares offsets[-1] with the capacity itself).  record: the fill writes
+    rows from the hits the count pass recorded (same result, larger
+    workspace)."""
     torch = _torch()
     L = B.load()
     if queries is not None:
@@ -182,6 +188,8 @@ def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, c
     indices = torch.empty(max(int(capacity), 1), dtype=torch.int32, device="cuda")
     B.check(L.radius_search(*args, _ptr(indices), int(capacity), flags, _ptr(ws), ctypes.byref(need), stream),
             "radius_search")
+    if check:
+        B.check_capacity(offsets, nq, int(capacity), stream, "radius_search")
     return counts, offsets, indices
 
 
@@ -337,12 +345,13 @@ def _query_rows(torch, batch, queries, q_sizes):
 
 
 def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphere", r=1.0,
-                          capacity: int | None = None, prune: bool = True, record: bool = False):
+                          capacity: int | None = None, prune: bool = True, record: bool = False,
+                          check: bool = True):
     """Radius search of every cloud of the batch (its own kernel and radius)
     in one launch per pass.  One CSR over all rows (cloud c's rows follow
     cloud c - 1's); indices are local to each cloud.  queries=None: every
-    cloud's own points, rows in each cloud's sorted order.  record: as for
-    radius_search."""
+    cloud's own points, rows in each cloud's sorted order.  capacity,
+    record, check: as for radius_search."""
     torch = _torch()
     L = B.load()
     kernels = _per_cloud(kernel, batch.B, "kernel")
@@ -371,6 +380,8 @@ def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphe
     indices = torch.empty(max(int(capacity), 1), dtype=torch.int32, device="cuda")
     B.check(L.radius_search_batched(*head, _ptr(indices), int(capacity), flags, _ptr(ws), ctypes.byref(need),
                                     stream), "radius_search_batched")
+    if check:
+        B.check_capacity(offsets, nq, int(capacity), stream, "radius_search_batched")
     return counts, offsets, indices
 
 

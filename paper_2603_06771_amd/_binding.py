@@ -21,7 +21,8 @@ REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED, RECORD_HITS = 1, 2, 4, 8
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
            "octree_batch_layout", "build_linear_octree_batched", "radius_search_batched", "knn_search_batched",
-           "radius_search_struct", "knn_locality", "gather_points", "sfc_last_error", "sfc_version")
+           "radius_search_struct", "knn_locality", "gather_points", "radius_search_check", "sfc_last_error",
+           "sfc_version")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -61,6 +62,15 @@ class SfcError(RuntimeError):
     pass
 
 
+class SfcCapacityError(SfcError):
+    """The neighbour total exceeds the output capacity; nothing was written.
+    `total` is the capacity a second call needs."""
+
+    def __init__(self, msg: str, total: int):
+        super().__init__(msg)
+        self.total = int(total)
+
+
 _lib = None
 
 
@@ -88,12 +98,25 @@ def load(path: str = LIB_PATH):
     L.radius_search_struct.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, F32, P, P, P, U64, P, P, P, U64, U32,
                                        P, ctypes.POINTER(SZ), P]
     L.knn_locality.argtypes = [ctypes.POINTER(SfcOctree), P, I64, P, I32, I32, P, P, P, ctypes.POINTER(SZ), P]
+    L.radius_search_check.argtypes = [P, I64, U64, ctypes.POINTER(U64), P]
     L.sfc_last_error.restype = ctypes.c_char_p
     L.sfc_version.restype = ctypes.c_char_p
     for name in EXPORTS[:-2]:
         getattr(L, name).restype = I32
     _lib = L
     return L
+
+
+def check_capacity(offsets, nq: int, capacity: int, stream, what: str) -> int:
+    """radius_search_check on a device offsets array: returns the neighbour
+    total, raises SfcCapacityError when it exceeds `capacity`."""
+    total = U64(0)
+    rc = load().radius_search_check(ctypes.c_void_p(offsets.data_ptr()), int(nq), int(capacity), ctypes.byref(total),
+                                    stream)
+    if rc == SFC_ECAPACITY:
+        raise SfcCapacityError(f"{what}: {load().sfc_last_error().decode(errors='replace')}", total.value)
+    check(rc, what)
+    return int(total.value)
 
 
 def check(rc: int, what: str) -> None:

@@ -42,7 +42,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -434,6 +436,12 @@ struct SearchArgs {
     uint32_t *rec_idx;
     uint64_t *rec_mask;
     uint32_t *rec_n;          // records of each group; kRecOverflow: did not fit
+    // provenance of the records: the recording count stamps (tag0, tag1) into
+    // rec_tag; a fill uses the records only if rec_tag holds its own pair
+    // (the number the host gave the workspace's last count call, and a hash
+    // of the call's arguments), else it searches again
+    uint64_t *rec_tag;
+    uint64_t tag0, tag1;
 };
 
 // Query of a lane (position lr in its cloud's rows) and the global row its
@@ -1416,6 +1424,12 @@ __global__ __launch_bounds__(64) void k_struct_fill(SearchArgs a) {
 }
 
 namespace {
+
+// do the workspace's records come from the count call this fill follows?
+__device__ __forceinline__ bool records_valid(const SearchArgs &a) {
+    return a.rec_tag && a.rec_tag[0] == a.tag0 && a.rec_tag[1] == a.tag1;
+}
+
 }  // namespace
 
 // One wave per group of 64 queries of one cloud; the cloud's kernel selects
@@ -1439,6 +1453,10 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
     __shared__ RadLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
+    if (g == 0 && lane_id() == 0) {  // the records' provenance (read by the fills, which run after this kernel)
+        a.rec_tag[0] = a.tag0;
+        a.rec_tag[1] = a.tag1;
+    }
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.kernel) {
@@ -1456,6 +1474,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    if (!records_valid(a)) return;                   // k_radius_fill searches every group
     const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
     if (v == kRecOverflow || (v & kRecLongRows)) return;
     const SearchCloud C = group_cloud(a, g);
@@ -1469,6 +1488,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_rec_long(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    if (!records_valid(a)) return;                   // k_radius_fill searches every group
     const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
     if (v == kRecOverflow || !(v & kRecLongRows)) return;
     const SearchCloud C = group_cloud(a, g);
@@ -1481,7 +1501,7 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
-    if (a.rec_n && a.rec_n[g] != kRecOverflow) return;  // written from its records
+    if (a.rec_n && records_valid(a) && a.rec_n[g] != kRecOverflow) return;  // written from its records
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.kernel) {
@@ -2073,6 +2093,7 @@ struct SearchWs {
     uint32_t *rec_idx = nullptr;
     uint64_t *rec_mask = nullptr;
     uint32_t *rec_n = nullptr;
+    uint64_t *rec_tag = nullptr;
 };
 
 bool wants_order(const float *queries, int64_t nq_total, uint32_t flags) {
@@ -2100,6 +2121,7 @@ size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem
         x.rec_idx = c.take<uint32_t>(groups * kRecCap);
         x.rec_mask = c.take<uint64_t>(groups * kRecCap);
         x.rec_n = c.take<uint32_t>(groups);
+        x.rec_tag = c.take<uint64_t>(2);
     }
     c.take<char>(256);
     if (w) *w = x;
@@ -2128,6 +2150,47 @@ int order_queries(SearchArgs &a, const SearchWs &w, hipStream_t s) {
     return SFC_OK;
 }
 
+// Provenance of recorded hits.  Every count call on a workspace gets a new
+// number (0 when it records nothing); a recording count stamps the number
+// and a hash of its arguments into the workspace, and a fill that reuses the
+// counts (SFC_REUSE_COUNTS) expects the pair of the last count call on the
+// same workspace address with its own arguments.  A fill after a count that
+// did not record, on another workspace or with other arguments finds a
+// different pair and searches instead of reading the records.
+std::mutex g_tag_mu;
+std::unordered_map<uintptr_t, uint64_t> g_tag_last;  // workspace address -> number of its last count call
+uint64_t g_tag_next = 1;
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+void record_provenance(SearchArgs &a, const std::vector<SearchCloud> &tab, void *ws, uint64_t *tag, bool record) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    h = fnv1a(h, tab.data(), tab.size() * sizeof(SearchCloud));
+    const uintptr_t ptrs[4] = {reinterpret_cast<uintptr_t>(a.queries), reinterpret_cast<uintptr_t>(a.counts),
+                               reinterpret_cast<uintptr_t>(a.offsets), static_cast<uintptr_t>(a.nq_total)};
+    h = fnv1a(h, ptrs, sizeof ptrs);
+    const uint32_t nf = a.flags & SFC_NO_PRUNE;
+    h = fnv1a(h, &nf, sizeof nf);
+    std::lock_guard<std::mutex> lock(g_tag_mu);
+    uint64_t &last = g_tag_last[reinterpret_cast<uintptr_t>(ws)];
+    if (!(a.flags & SFC_REUSE_COUNTS)) last = record ? g_tag_next++ : 0;
+    a.tag0 = last;
+    a.tag1 = h;
+    if (!record || last == 0) {
+        a.rec_tag = nullptr;  // no records to read: every group is searched
+        a.rec_n = nullptr;
+    } else {
+        a.rec_tag = tag;
+    }
+}
+
 int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t groups, uint32_t *counts,
                   void *ws, hipStream_t s) {
     const int B = static_cast<int>(tab.size());
@@ -2140,6 +2203,7 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
         a.rec_mask = w.rec_mask;
         a.rec_n = w.rec_n;
     }
+    record_provenance(a, tab, ws, w.rec_tag, record);
     SearchCloud *dtab = w.tab;
     void *scan_ws = w.scan;
     a.one = tab[0];
@@ -2412,8 +2476,8 @@ extern "C" int knn_search(const sfc_octree *tree, const float *queries, int64_t 
         *ws_bytes = need;
         return SFC_OK;
     }
-    if (*ws_bytes < need) {
-        set_error("knn_search: workspace needs %zu bytes", need);
+    if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("knn_search: workspace needs %zu bytes, 256-aligned", need);
         return SFC_EWORKSPACE;
     }
     std::vector<SearchCloud> tab(1, cloud_entry(*tree, 0, nq, 0, SFC_SPHERE, 0.0f, k));
@@ -2458,3 +2522,23 @@ extern "C" int knn_search_batched(int B, const sfc_cloud *clouds, const float *q
     a.d2 = d2;
     return knn_launch(a, tab, groups, kmax, ws, static_cast<hipStream_t>(stream));
 }
+
+extern "C" int radius_search_check(const uint64_t *offsets, int64_t nq, uint64_t capacity, uint64_t *total,
+                                   void *stream) {
+    if (!offsets || nq < 0 || !total) {
+        set_error("radius_search_check: invalid argument");
+        return SFC_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t t = 0;
+    SFC_HIP_TRY(hipMemcpyAsync(&t, offsets + nq, sizeof t, hipMemcpyDeviceToHost, s));
+    SFC_HIP_TRY(hipStreamSynchronize(s));
+    *total = t;
+    if (t > capacity) {
+        set_error("radius_search_check: %llu neighbour indices exceed the capacity %llu; no index was written",
+                  static_cast<unsigned long long>(t), static_cast<unsigned long long>(capacity));
+        return SFC_ECAPACITY;
+    }
+    return SFC_OK;
+}
+

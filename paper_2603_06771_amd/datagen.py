@@ -103,11 +103,12 @@ def with_duplicates(pts: np.ndarray, n_dup: int, seed: int = 7) -> np.ndarray:
     return np.concatenate([pts, pts[pick]], axis=0)
 
 
-def batch_mix(n_clouds: int = 256, seed: int = SEED_BATCH, n_min: float = 1e4, n_max: float = 2e6):
-    """List of cloud descriptors {points, kernel, radius} for the batched workload.
+def batch_mix_specs(n_clouds: int = 256, seed: int = SEED_BATCH, n_min: float = 1e4, n_max: float = 2e6):
+    """Descriptors {n, kind, kernel, radius, seed} of the clouds of batch_mix,
+    without generating the points (so a test can pick some of them).
 
-    Sizes are log-uniform in [n_min, n_max]; even-numbered draws are uniform
-    clouds of one point per cubic metre, odd-numbered LiDAR tiles; the radius is
+    Sizes are log-uniform in [n_min, n_max]; each cloud is uniform (one point
+    per cubic metre) or a LiDAR tile with probability 1/2; the radius is
     U(0.5, 3) m and the kernel uniform over the four kernels."""
     rng = _rng(seed)
     kernels = ["sphere", "circle", "cube", "square"]
@@ -115,12 +116,26 @@ def batch_mix(n_clouds: int = 256, seed: int = SEED_BATCH, n_min: float = 1e4, n
     for i in range(int(n_clouds)):
         n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
         kind = "uniform" if rng.random() < 0.5 else "lidar"
-        if kind == "uniform":
-            pts = uniform(n, seed=seed + 1 + i, side=float(n) ** (1.0 / 3.0))
-        else:
-            pts = lidar_tile(n, seed=seed + 1 + i)
-        out.append({"points": pts, "kind": kind, "kernel": kernels[int(rng.integers(0, 4))],
-                    "radius": float(np.float32(rng.uniform(0.5, 3.0)))})
+        out.append({"n": n, "kind": kind, "kernel": kernels[int(rng.integers(0, 4))],
+                    "radius": float(np.float32(rng.uniform(0.5, 3.0))), "seed": seed + 1 + i})
+    return out
+
+
+def batch_cloud(spec) -> np.ndarray:
+    """The points of one batch_mix_specs descriptor."""
+    n = spec["n"]
+    if spec["kind"] == "uniform":
+        return uniform(n, seed=spec["seed"], side=float(n) ** (1.0 / 3.0))
+    return lidar_tile(n, seed=spec["seed"])
+
+
+def batch_mix(n_clouds: int = 256, seed: int = SEED_BATCH, n_min: float = 1e4, n_max: float = 2e6):
+    """List of cloud descriptors {points, kind, kernel, radius} for the batched
+    workload (see batch_mix_specs)."""
+    out = []
+    for spec in batch_mix_specs(n_clouds, seed, n_min, n_max):
+        out.append({"points": batch_cloud(spec), "kind": spec["kind"], "kernel": spec["kernel"],
+                    "radius": spec["radius"]})
     return out
 
 

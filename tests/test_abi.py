@@ -167,4 +167,25 @@ def test_record_hits_workspace_size(lib):
                                  ctypes.byref(rec), None) == B.SFC_OK
         groups = (n + 63) // 64
         assert rec.value - plain.value >= groups * 4096 * 12 + groups * 4
-        assert rec.value - plain.value <= (n // 64 + 2) * (4096 * 12 + 4) + 3 * 256
+        assert rec.value - plain.value <= (n // 64 + 2) * (4096 * 12 + 4) + 4 * 256
+
+
+def test_workspace_alignment_and_capacity_check_validation(lib):
+    view = B.SfcOctree()
+    view.nodes = view.child = view.points = view.keys = view.frame = 256
+    view.n = 1000
+    fake = ctypes.c_void_p(256)
+    need = ctypes.c_size_t(0)
+    assert lib.knn_search(ctypes.byref(view), None, 1000, 8, fake, fake, None, ctypes.byref(need), None) == B.SFC_OK
+    big = ctypes.c_size_t(need.value + 4096)
+    # a workspace that is not 256-byte aligned is refused before anything runs
+    assert lib.knn_search(ctypes.byref(view), None, 1000, 8, fake, fake, ctypes.c_void_p(256 + 64),
+                          ctypes.byref(big), None) == B.SFC_EWORKSPACE
+    assert b"256-aligned" in lib.sfc_last_error()
+    assert lib.radius_search(ctypes.byref(view), None, 1000, 0, 1.0, fake, fake, None, 0, 0,
+                             ctypes.c_void_p(256 + 8), ctypes.byref(big), None) == B.SFC_EWORKSPACE
+    # the capacity check validates its arguments on the host
+    total = ctypes.c_uint64(0)
+    assert lib.radius_search_check(None, 10, 0, ctypes.byref(total), None) == B.SFC_EINVAL
+    assert lib.radius_search_check(fake, -1, 0, ctypes.byref(total), None) == B.SFC_EINVAL
+    assert lib.radius_search_check(fake, 10, 0, None, None) == B.SFC_EINVAL

@@ -137,10 +137,13 @@ def test_batch_radius_capacity(sfc):
     import torch
     batch, clouds = _mixed_batch(sfc)
     announce("batch radius, capacity too small then exact")
-    c, o, _ = sfc.radius_search_batched(batch, None, None, "sphere", 0.5, capacity=5)
+    c, o, _ = sfc.radius_search_batched(batch, None, None, "sphere", 0.5, capacity=5, check=False)
     torch.cuda.synchronize()
     total = int(o[-1])
     assert total > 5
+    with pytest.raises(sfc.SfcCapacityError) as e:
+        sfc.radius_search_batched(batch, None, None, "sphere", 0.5, capacity=total - 1)
+    assert e.value.total == total
     c2, o2, i2 = sfc.radius_search_batched(batch, None, None, "sphere", 0.5, capacity=total)
     torch.cuda.synchronize()
     assert torch.equal(c, c2) and torch.equal(o, o2)
@@ -231,4 +234,68 @@ def test_many_small_clouds(sfc):
         ridx, rd2 = oracle.knn(pts, pts[perm], ks[c])
         assert np.array_equal(gi[q0:q0 + n, :ks[c]], ridx), f"cloud {c}: knn indices"
         assert np.array_equal(gd[q0:q0 + n, :ks[c]].view(np.uint32), rd2.view(np.uint32)), f"cloud {c}: knn d2"
+        q0 += n
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("record", [False, True])
+def test_batch_mix_largest_clouds(sfc, record):
+    """The four largest clouds of the 256-cloud batch mix (1.76M-1.86M points,
+    uniform and LiDAR, cube and circle kernels, r = 1.4-2.3 m) and its four
+    smallest, built and searched in one batch as the batched benchmark runs
+    them (Hilbert, leaf 64 and 128): every row's count against the oracle's,
+    sampled rows and k-NN rows element by element."""
+    import torch
+    specs = datagen.batch_mix_specs(256, seed=datagen.SEED_BATCH)
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
+    pick = order[-4:] + order[:4]
+    sp = [specs[i] for i in pick]
+    clouds = [datagen.batch_cloud(s) for s in sp]
+    sizes = [c.shape[0] for c in clouds]
+    leafs = [64, 128, 64, 128, 64, 128, 64, 128]
+    kern = [s["kernel"] for s in sp]
+    radii = [s["radius"] for s in sp]
+    announce(f"batch mix largest/smallest clouds {sizes} record={record}")
+    batch = sfc.build_batch(_dev(np.concatenate(clouds)), sizes, "hilbert", 21, leafs)
+    c, o, i = sfc.radius_search_batched(batch, None, None, kern, radii, record=record)
+    torch.cuda.synchronize()
+    c, o = c.cpu().numpy(), o.cpu().numpy()
+    rng = np.random.default_rng(23)
+    q0 = 0
+    for cl, pts in enumerate(clouds):
+        n = pts.shape[0]
+        perm = batch.tree(cl).perm().cpu().numpy().view(np.uint32)
+        dims = 2 if kern[cl] in ("circle", "square") else 3
+        grid = oracle.Grid(pts, radii[cl], dims)
+        rc = grid.radius_count(pts, kern[cl], radii[cl])
+        got = c[q0:q0 + n].view(np.uint32)
+        bad = np.nonzero(got != rc[perm])[0]
+        assert bad.size == 0, f"cloud {cl}: {bad.size} counts differ"
+        rows = np.sort(rng.choice(n, min(n, 300), replace=False))
+        ref_c, ref_o, ref_i = grid.radius_search(pts[perm[rows]], kern[cl], radii[cl])
+        for k, row in enumerate(rows):
+            a, b = int(o[q0 + row]), int(o[q0 + row + 1])
+            g = np.sort(i[a:b].cpu().numpy().view(np.uint32))
+            assert np.array_equal(g, ref_i[ref_o[k]:ref_o[k + 1]]), f"cloud {cl} row {row}"
+        del grid
+        q0 += n
+    del i
+    torch.cuda.empty_cache()
+    if record:
+        return
+    ks = [16, 32, 8, 16, 32, 8, 16, 32]
+    announce("batch mix largest/smallest clouds: knn")
+    idx, d2 = sfc.knn_search_batched(batch, None, None, ks, kstride=32)
+    torch.cuda.synchronize()
+    q0 = 0
+    for cl, pts in enumerate(clouds):
+        n = pts.shape[0]
+        perm = batch.tree(cl).perm().cpu().numpy().view(np.uint32)
+        rows = np.sort(rng.choice(n, min(n, 500), replace=False))
+        ridx, rd2 = oracle.knn(pts, pts[perm[rows]], ks[cl])
+        sel = torch.from_numpy(q0 + rows).cuda()
+        gi = idx[sel].cpu().numpy().view(np.uint32)
+        gd = d2[sel].cpu().numpy()
+        assert np.array_equal(gi[:, :ks[cl]], ridx), f"cloud {cl}: knn indices"
+        assert np.array_equal(gd[:, :ks[cl]].view(np.uint32), rd2.view(np.uint32)), f"cloud {cl}: knn d2"
         q0 += n

@@ -205,10 +205,14 @@ def test_radius_capacity_protocol(sfc):
     pts = _cloud("uniform", 20000, seed=6)
     t = sfc.build_linear_octree(_dev(pts), "morton", 21, 32)
     announce("radius capacity too small")
-    c, o, i = sfc.radius_search(t, None, "sphere", 0.05, capacity=10)
+    c, o, i = sfc.radius_search(t, None, "sphere", 0.05, capacity=10, check=False)
     torch.cuda.synchronize()
     total = int(o[-1])
     assert total > 10
+    # the checked form raises, with the capacity a second call needs
+    with pytest.raises(sfc.SfcCapacityError) as e:
+        sfc.radius_search(t, None, "sphere", 0.05, capacity=total - 1)
+    assert e.value.total == total
     # nothing written: the buffer keeps whatever it held, the counts are valid
     c2, o2, i2 = sfc.radius_search(t, None, "sphere", 0.05, capacity=total)
     torch.cuda.synchronize()
