@@ -11,11 +11,12 @@ import oracle
 from paper_2603_06771_amd import datagen
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "locality_line.txt")
+GOLD_SKEWED = os.path.join(os.path.dirname(__file__), "golden", "locality_skewed.txt")
 
 
-def _gold():
+def _gold(path=GOLD):
     out = {}
-    for line in open(GOLD):
+    for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
         key, *vals = line.split()
@@ -38,6 +39,32 @@ def test_hand_worked_line():
     idx, _ = oracle.knn(rev, rev, k)
     H, _ = oracle.locality_histogram(np.arange(5)[::-1], np.arange(5)[::-1][idx])
     assert list(H) == [int(v) for v in g["reversed_hist"]]
+
+
+def test_hand_worked_skewed():
+    """An asymmetric example: one pair at distance 3 among pairs at distance
+    1 gives G1 = 352/243 (worked by hand in the fixture)."""
+    g = _gold(GOLD_SKEWED)
+    x = np.array(g["points"], np.float32)
+    pts = np.stack([x, np.zeros_like(x), np.zeros_like(x)], axis=1)
+    k = int(g["k"][0])
+    idx, _ = oracle.knn(pts, pts, k)
+    H, st = oracle.locality_histogram(np.arange(5), idx)
+    assert list(H) == [int(v) for v in g["hist"]]
+    for key in ("total", "mean", "std", "g1", "q1", "q2", "q3", "max"):
+        assert abs(st[key] - g[key][0]) < 1e-12, key
+    assert abs(st["g1"] - 352.0 / 243.0) < 1e-12
+
+
+def _random_order_g1(k: int) -> float:
+    """Skewness of the full histogram under a random storage order: a point
+    mass at 0 (the centre, weight 1/k) mixed with the triangular law of
+    |U1 - U2| on [0, 1] (density 2(1 - t); raw moments 1/3, 1/6, 1/10)."""
+    w = 1.0 - 1.0 / k
+    m1, m2, m3 = w / 3.0, w / 6.0, w / 10.0
+    var = m2 - m1 * m1
+    mu3 = m3 - 3.0 * m1 * m2 + 2.0 * m1 ** 3
+    return mu3 / var ** 1.5
 
 
 def _sorted_cloud(n, curve, seed):
@@ -77,7 +104,9 @@ def test_random_order_skewness():
     g1 = (w * ((d - m) / s) ** 3).sum()
     assert abs(m / n - 1.0 / 3.0) < 0.01
     assert abs(g1 - 2.0 * np.sqrt(2.0) / 5.0) < 0.03
-    assert st["g1"] < 1.0
+    # with the centres: the point mass at 0 mixed with the triangular law
+    assert abs(st["g1"] - _random_order_g1(k)) < 0.03
+    assert abs(st["mean"] / n - (1.0 - 1.0 / k) / 3.0) < 0.01
 
 
 def test_subset_rows():
