@@ -200,6 +200,27 @@ int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int 
  * host; it allocates nothing.  SFC_EHIP if the copy or the wait fails. */
 int radius_search_check(const uint64_t *offsets, int64_t nq, uint64_t capacity, uint64_t *total, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * radius_search with the same arguments, results and capacity protocol,
+ * but no workspace argument.  Its workspace is a fixed array of
+ * SFC_NOALLOC_SCRATCH_BYTES bytes inside this library, one per GPU, taken
+ * when the library is loaded and held until the process ends; the call
+ * allocates nothing.  A call whose workspace (the size radius_search would
+ * ask for) exceeds it returns SFC_EWORKSPACE and does nothing: 64 MiB covers
+ * up to about a billion queries around a cloud's own points (queries ==
+ * NULL) or already ordered (SFC_QUERIES_ORDERED), and about 2.6 million
+ * external queries that the call sorts; SFC_RECORD_HITS takes about 48 KB
+ * per 64 queries of it.  All calls on one GPU share the array, which
+ * keeps the last call's contents: calls that overlap on one GPU (two
+ * streams, two host threads) race and give undefined results; calls in
+ * one stream are ordered and safe.  Arguments, layouts, ownership and the
+ * other errors are those of radius_search. */
+#define SFC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int radius_search_noalloc(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
+                          uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
+                          uint32_t flags, void *stream);
+
 /* Section 5.1, the neighboursStruct form of radius_search: the same
  * neighbour set per query, split into the ranges of sorted positions of the
  * octree nodes that lie entirely inside the neighbourhood and the individual

@@ -2542,3 +2542,63 @@ extern "C" int radius_search_check(const uint64_t *offsets, int64_t nq, uint64_t
     return SFC_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// radius_search without a caller workspace: the workspace is a fixed device
+// array of this library (one per GPU, held until the process ends), for
+// callers that cannot allocate device memory.  Host code never passes the
+// array's name to a kernel (in host code it is a stand-in, not a device
+// address): the device address is looked up once per device and kept.
+namespace {
+
+constexpr size_t kScratchBytes = SFC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kScratchDevices] = {};
+
+// device address of the current device's scratch array (looked up on the
+// first call on that device, with the device current)
+int scratch_ptr(void **out) {
+    int dev = -1;
+    SFC_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("radius_search_noalloc: device %d beyond the %d supported", dev, kScratchDevices);
+        return SFC_ENOTSUP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("radius_search_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return SFC_EHIP;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" int radius_search_noalloc(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
+                                     uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
+                                     uint32_t flags, void *stream) {
+    size_t need = 0;
+    int rc = radius_search(tree, queries, nq, kernel, r, counts, offsets, indices, capacity, flags, nullptr, &need,
+                           stream);
+    if (rc) return rc;
+    if (need > kScratchBytes) {
+        set_error("radius_search_noalloc: the call needs %zu bytes of workspace, beyond the fixed %zu "
+                  "(fewer external queries per call, or radius_search with a workspace)",
+                  need, kScratchBytes);
+        return SFC_EWORKSPACE;
+    }
+    void *ws = nullptr;
+    rc = scratch_ptr(&ws);
+    if (rc) return rc;
+    size_t have = kScratchBytes;
+    return radius_search(tree, queries, nq, kernel, r, counts, offsets, indices, capacity, flags, ws, &have, stream);
+}

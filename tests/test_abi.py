@@ -189,3 +189,31 @@ def test_workspace_alignment_and_capacity_check_validation(lib):
     assert lib.radius_search_check(None, 10, 0, ctypes.byref(total), None) == B.SFC_EINVAL
     assert lib.radius_search_check(fake, -1, 0, ctypes.byref(total), None) == B.SFC_EINVAL
     assert lib.radius_search_check(fake, 10, 0, None, None) == B.SFC_EINVAL
+
+
+def test_noalloc_host_checks(lib):
+    """radius_search_noalloc validates its arguments and refuses a call whose
+    workspace exceeds the fixed array before any GPU work (or HIP call)."""
+    text = open(HEADER).read()
+    limit = int(re.search(r"#define SFC_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text).group(1)) << 20
+    view = B.SfcOctree()
+    fake = ctypes.c_void_p(256)
+    # an all-null tree view is rejected
+    assert lib.radius_search_noalloc(ctypes.byref(view), None, 0, 0, 1.0, fake, fake, None, 0, 0, None) \
+        == B.SFC_EINVAL
+    view.nodes = view.child = view.points = view.keys = view.frame = 256
+    view.n = 100_000
+    assert lib.radius_search_noalloc(ctypes.byref(view), None, 100_000, 9, 1.0, fake, fake, None, 0, 0, None) \
+        == B.SFC_EINVAL  # kernel out of range
+    # recorded hits for 100k queries need more than the fixed array: refused
+    need = ctypes.c_size_t(0)
+    assert lib.radius_search(ctypes.byref(view), None, 100_000, 0, 1.0, fake, fake, None, 0, B.RECORD_HITS, None,
+                             ctypes.byref(need), None) == B.SFC_OK
+    assert need.value > limit
+    assert lib.radius_search_noalloc(ctypes.byref(view), None, 100_000, 0, 1.0, fake, fake, None, 0,
+                                     B.RECORD_HITS, None) == B.SFC_EWORKSPACE
+    assert b"beyond the fixed" in lib.sfc_last_error()
+    # external queries that the call sorts: about 24 bytes each, so 3M of them are refused
+    view.n = 1000
+    assert lib.radius_search_noalloc(ctypes.byref(view), fake, 3_000_000, 0, 1.0, fake, fake, None, 0, 0, None) \
+        == B.SFC_EWORKSPACE
