@@ -65,8 +65,7 @@ def parse():
                     help="radius: the fill searches again instead of writing rows from the hits the count "
                          "pass recorded (SFC_RECORD_HITS, the default)")
     ap.add_argument("--record-batched", action="store_true",
-                    help="batched: fill from recorded hits (slower on this mix: dense clouds overflow the records "
-                         "and their contained nodes are tested point by point)")
+                    help="batched: fill every cloud from recorded hits instead of the autotuner's per-group choice")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--workload", default="radius", choices=["radius", "batched", "served", "subset"],
@@ -115,6 +114,13 @@ def _events(torch, n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
 
+def _count(items) -> dict:
+    out = {}
+    for x in items:
+        out[x] = out.get(x, 0) + 1
+    return out
+
+
 def bench_batched(args):
     """256 independent clouds (log-uniform 1e4..2e6 points, uniform / LiDAR,
     per-cloud kernel and radius): build + radius search of every cloud.
@@ -138,12 +144,11 @@ def bench_batched(args):
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     log(f"[bench] generated {len(sizes)} clouds, {n} points in {time.perf_counter() - t0:.1f} s")
 
-    tune = autotune.tune_leaf(xyz, sizes, kernels, radii, "hilbert", repeats=args.tune_repeats,
-                              cache_path=os.path.join(tempfile.gettempdir(), "sfcoct_bench_autotune.json"), log=log)
-    leaves = tune["leaf"]
-
-    record = bool(args.record_batched)
-    plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii, record=record)
+    tune = autotune.tune(xyz, sizes, kernels, radii, "hilbert", repeats=args.tune_repeats,
+                         cache_path=os.path.join(tempfile.gettempdir(), "sfcoct_bench_autotune.json"), log=log)
+    leaves, stages = tune["leaf"], tune["stage"]
+    record = [True] * len(sizes) if args.record_batched else tune["record"]
+    plan = BatchPlan(xyz, sizes, "hilbert", 21, leaves, kernels, radii, record=record, stage=stages)
     total = plan.total()
     log(f"[bench] batched plan: {total} neighbours ({total * 4 / 1e9:.2f} GB)")
 
@@ -190,7 +195,7 @@ def bench_batched(args):
     # baseline: one launch sequence per cloud
     starts = np.concatenate([[0], np.cumsum(sizes)])
     singles = [BatchPlan(xyz[starts[c]:starts[c + 1]], [sizes[c]], "hilbert", 21, leaves[c], kernels[c], radii[c],
-                         record=record) for c in range(len(sizes))]
+                         record=record[c], stage=stages[c]) for c in range(len(sizes))]
 
     def per_cloud():
         for p in singles:
@@ -212,8 +217,11 @@ def bench_batched(args):
     base_graph_wall, base_graph_gpu = timed(g.replay, args.steps)
     log(f"[bench] per-cloud eager {base_wall:.2f} ms, graph {base_graph_wall:.2f} ms per step; counts equal: {same}")
 
-    # the fill stage's algorithmic bytes (the search fill also reads every point)
-    fill_bytes = 8 * (n + 1) + 4 * total if record else 16 * n + 8 * (n + 1) + 4 * total
+    # algorithmic bytes of the searches (every point a query): the point read
+    # once, its count and row offset written, 4 B per neighbour (the tree's
+    # node bytes, under 2 % at these leaf sizes, left out)
+    search_bytes = (16 + 4 + 8) * n + 8 + 4 * total
+    search_ms = stage_ms["count+scan"] + stage_ms["fill"]
     out = {
         "metric": "batched build + radius-search queries/s (256 clouds, one HIP graph)",
         "value": n / (graph_wall / 1e3),
@@ -228,8 +236,9 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batch256_mix_build_radius", "clouds": len(sizes), "points": n,
-                   "neighbours": total, "curve": "hilbert", "leaf": "autotuned per mu group",
-                   "record_hits": record},
+                   "neighbours": total, "curve": "hilbert",
+                   "leaf_stage_fill": "autotuned per mu group" + (", every cloud recorded" if args.record_batched
+                                                                  else "")},
         "batched": {"graph_ms": round(graph_wall, 3), "graph_gpu_ms": round(graph_gpu, 3),
                     "eager_ms": round(eager_wall, 3), "eager_gpu_ms": round(eager_gpu, 3), "stages_ms": stage_ms},
         "one_launch_sequence_per_cloud": {"eager_ms": round(base_wall, 3), "eager_gpu_ms": round(base_gpu, 3),
@@ -237,12 +246,14 @@ def bench_batched(args):
                                           "graph_gpu_ms": round(base_graph_gpu, 3), "counts_equal": same},
         "speedup_vs_per_cloud": {"eager": base_wall / eager_wall, "graph": base_graph_wall / graph_wall,
                                  "graph_vs_per_cloud_eager": base_wall / graph_wall},
-        "roofline": {"bound": "hbm", "kernel": FILL_STAGE if record else "k_radius_fill",
-                     "achieved": fill_bytes / stage_ms["fill"] / 1e6,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_bytes / stage_ms["fill"] / 1e6 / HBM_PEAK_GBS,
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": "radius_search_batched (count + scan + fill)",
+                     "achieved": search_bytes / search_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": search_bytes / search_ms / 1e6 / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_query": "16 + 4 + 8 + 4 mu"},
         "autotune": {"table_ms": tune["table"], "mu_edges": tune["edges"], "cached": tune["cached"],
-                     "leaf_histogram": {str(k): int(v) for k, v in zip(*np.unique(leaves, return_counts=True))}},
+                     "choice_histogram": {f"leaf={lf}/stage={st}/fill={'record' if rc else 'search'}": cnt
+                                          for (lf, st, rc), cnt in
+                                          sorted(_count(zip(leaves, stages, record)).items())}},
     }
     print(json.dumps(out), flush=True)
 

@@ -176,6 +176,12 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
  *             workspace or with other arguments, or a later count call used
  *             the workspace) searches instead, so the result is the same
  *             with or without the bit.
+ *             bits 4-5 (SFC_STAGE_64, SFC_STAGE_256): the search's staging
+ *             tile, the points staged in LDS per sweep round: 64 or 256
+ *             instead of 128 (both bits: SFC_EINVAL).  A larger round
+ *             amortises per-round work over more points, a smaller one
+ *             keeps more waves resident; results are identical for every
+ *             tile.
  *
  * Capacity protocol: the indices are written only when the neighbour total
  * offsets[nq] fits `capacity`, which the kernels check on the device (no
@@ -186,6 +192,9 @@ int build_linear_octree(const float *xyz, int64_t n, int curve, int bits, uint32
 #define SFC_NO_PRUNE 2u
 #define SFC_QUERIES_ORDERED 4u
 #define SFC_RECORD_HITS 8u
+#define SFC_STAGE_64 16u
+#define SFC_STAGE_256 32u
+#define SFC_STAGE_MASK 48u
 int radius_search(const sfc_octree *tree, const float *queries, int64_t nq, int kernel, float r,
                   uint32_t *counts, uint64_t *offsets, uint32_t *indices, uint64_t capacity,
                   uint32_t flags, void *ws, size_t *ws_bytes, void *stream);
@@ -277,6 +286,9 @@ typedef struct sfc_cloud {
     int32_t k;           /* k-NN: 1..kstride (at most 512) */
     int64_t q_offset;    /* search: first row of the cloud in the concatenated queries */
     int64_t nq;          /* search: queries of the cloud (cloud queries: nq == n) */
+    uint32_t stage;      /* radius search: staging tile, points per sweep round (64, 128, 256; 0: 128) */
+    uint32_t record;     /* radius search: nonzero records the cloud's hits for the fill (as
+                            SFC_RECORD_HITS does for every cloud; workspace only for such clouds) */
     sfc_octree tree;     /* filled by octree_batch_layout */
 } sfc_cloud;
 
@@ -300,7 +312,12 @@ int build_linear_octree_batched(const float *xyz, int B, const sfc_cloud *clouds
  * (cloud c at rows [q_offset_c, q_offset_c + nq_c)), or NULL (each cloud's own
  * points, rows in the cloud's sorted order).  counts / offsets / indices form
  * ONE CSR over all nq_total rows (offsets[nq_total] = total), indices local to
- * each cloud.  Capacity and flags as for radius_search. */
+ * each cloud.  Capacity and flags as for radius_search, except the staging
+ * tile, which each cloud names itself (its `stage`; the flag bits are
+ * ignored), and recorded hits, which SFC_RECORD_HITS turns on for every
+ * cloud and a cloud's `record` for that cloud (the workspace holds records
+ * for the recording clouds' groups only).  An autotuner can so choose leaf
+ * size, tile and fill per cloud; every choice gives the same rows. */
 int radius_search_batched(int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total, uint32_t *counts,
                           uint64_t *offsets, uint32_t *indices, uint64_t capacity, uint32_t flags, void *ws,
                           size_t *ws_bytes, void *stream);

@@ -150,8 +150,15 @@ def build_linear_octree(xyz, curve="morton", bits: int = 21, leaf_size: int = 32
     return Octree(mem=mem, view=view, curve=c, bits=bits, leaf_size=leaf_size, n=n)
 
 
+def _stage_flag(stage) -> int:
+    try:
+        return B.STAGE_FLAGS[int(stage)]
+    except (KeyError, TypeError, ValueError):
+        raise ValueError(f"stage must be 64, 128 or 256, not {stage!r}") from None
+
+
 def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, capacity: int | None = None,
-                  prune: bool = True, record: bool = False, check: bool = True):
+                  prune: bool = True, record: bool = False, check: bool = True, stage: int = 128):
     """Section 3.2 / 5.1: CSR (counts int32, offsets int64 [nq+1], indices
     int32 original point indices).  queries=None searches around every cloud
     point, rows in sorted (curve) order.  Without a capacity the count pass
@@ -161,7 +168,8 @@ def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, c
     indices did not fit, unless check=False (no host wait: the caller
     compares offsets[-1] with the capacity itself).  record: the fill writes
     rows from the hits the count pass recorded (same result, larger
-    workspace)."""
+    workspace).  stage: the staging tile (points per sweep round: 64, 128
+    or 256; same result)."""
     torch = _torch()
     L = B.load()
     if queries is not None:
@@ -170,7 +178,7 @@ def radius_search(tree: Octree, queries=None, kernel="sphere", r: float = 1.0, c
     else:
         nq = tree.n
     k = _code(KERNELS, kernel)
-    flags = (0 if prune else B.NO_PRUNE) | (B.RECORD_HITS if record else 0)
+    flags = (0 if prune else B.NO_PRUNE) | (B.RECORD_HITS if record else 0) | _stage_flag(stage)
     counts = torch.empty(nq, dtype=torch.int32, device="cuda")
     offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)
@@ -345,22 +353,28 @@ def _query_rows(torch, batch, queries, q_sizes):
 
 
 def radius_search_batched(batch: Batch, queries=None, q_sizes=None, kernel="sphere", r=1.0,
-                          capacity: int | None = None, prune: bool = True, record: bool = False,
-                          check: bool = True):
+                          capacity: int | None = None, prune: bool = True, record=False,
+                          check: bool = True, stage=128):
     """Radius search of every cloud of the batch (its own kernel and radius)
     in one launch per pass.  One CSR over all rows (cloud c's rows follow
     cloud c - 1's); indices are local to each cloud.  queries=None: every
-    cloud's own points, rows in each cloud's sorted order.  capacity,
-    record, check: as for radius_search."""
+    cloud's own points, rows in each cloud's sorted order.  capacity, check:
+    as for radius_search; record and stage (the staging tile): one value or
+    one per cloud."""
     torch = _torch()
     L = B.load()
     kernels = _per_cloud(kernel, batch.B, "kernel")
     radii = _per_cloud(r, batch.B, "r")
+    records = _per_cloud(record, batch.B, "record")
+    stages = _per_cloud(stage, batch.B, "stage")
     for c in range(batch.B):
         batch.clouds[c].kernel = _code(KERNELS, kernels[c])
         batch.clouds[c].r = float(radii[c])
+        _stage_flag(stages[c])
+        batch.clouds[c].stage = int(stages[c])
+        batch.clouds[c].record = 1 if records[c] else 0
     queries, nq = _query_rows(torch, batch, queries, q_sizes)
-    flags = (0 if prune else B.NO_PRUNE) | (B.RECORD_HITS if record else 0)
+    flags = 0 if prune else B.NO_PRUNE
     counts = torch.empty(nq, dtype=torch.int32, device="cuda")
     offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)

@@ -17,6 +17,8 @@ SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_ECAPACITY, SFC_EHIP, SFC_ENOTSUP = 0, -1
 MORTON, HILBERT = 0, 1
 SPHERE, CIRCLE, CUBE, SQUARE = 0, 1, 2, 3
 REUSE_COUNTS, NO_PRUNE, QUERIES_ORDERED, RECORD_HITS = 1, 2, 4, 8
+STAGE_64, STAGE_256 = 16, 32
+STAGE_FLAGS = {64: STAGE_64, 128: 0, 256: STAGE_256}
 
 # every exported symbol of include/sfcoct.h
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
@@ -54,7 +56,8 @@ class SfcOctree(ctypes.Structure):
 class SfcCloud(ctypes.Structure):
     _fields_ = [
         ("offset", I64), ("n", I64), ("curve", I32), ("bits", I32), ("leaf_size", U32), ("kernel", I32),
-        ("r", F32), ("k", I32), ("q_offset", I64), ("nq", I64), ("tree", SfcOctree),
+        ("r", F32), ("k", I32), ("q_offset", I64), ("nq", I64), ("stage", U32), ("record", U32),
+        ("tree", SfcOctree),
     ]
 
 

@@ -1,20 +1,27 @@
-"""Leaf-size autotuner for batches of clouds.
+"""Autotuner of leaf size, staging tile and fill for batches of clouds.
 
 The best octree threshold N_max depends on how many neighbours a query has:
 small leaves prune finely when neighbourhoods are small, large leaves cut
-traversal work when they are large.  The tuner measures it instead of
+traversal work when they are large.  The search's staging tile (points
+staged in LDS per sweep round: 64, 128 or 256) trades per-round work
+against resident waves, and the fill either searches again or writes the
+rows from the hits the count pass recorded (faster for long rows, but
+48 KB of workspace per 64 queries).  The tuner measures instead of
 guessing:
 
   1. one counting step of the whole batch (leaf 32) gives every cloud's mean
      neighbour count mu;
   2. clouds are split into `buckets` groups by mu (quantiles);
   3. each group is built and searched as its own batch with every candidate
-     leaf size (median of `repeats` timed steps after a warm-up);
-  4. every cloud gets the fastest leaf size of its group.
+     leaf size at the default tile (stage 128, search fill), then, at the
+     fastest leaf, with every candidate (stage, fill) pair (median of
+     `repeats` timed steps after a warm-up each); recorded fills are tried
+     only while the group's records fit `record_budget` bytes;
+  4. every cloud gets its group's fastest (leaf, stage, fill).
 
 Results are cached in a JSON file keyed by the batch description (sizes,
-kernels, radii, curve, candidates, device name), so a repeated workload skips
-the measurement.
+kernels, radii, curve, candidates, budget, device name), so a repeated
+workload skips the measurement.
 """
 from __future__ import annotations
 
@@ -27,6 +34,10 @@ import numpy as np
 from .plan import BatchPlan
 
 CANDIDATES = (16, 32, 64, 128)
+STAGES = (64, 128, 256)
+FILLS = ("search", "record")
+RECORD_BYTES_PER_GROUP = 4096 * 12  # recorded hits: 4096 (index, mask) slots per 64 queries
+DEFAULT_RECORD_BUDGET = 64 << 30
 
 
 def default_cache_path() -> str:
@@ -34,10 +45,11 @@ def default_cache_path() -> str:
     return os.path.join(base, "sfcoct", "autotune.json")
 
 
-def _key(sizes, kernels, radii, curve, candidates, buckets, device) -> str:
+def _key(sizes, kernels, radii, curve, candidates, stages, fills, buckets, budget, device) -> str:
     h = hashlib.sha256()
     h.update(json.dumps([list(map(int, sizes)), list(map(str, kernels)), [float(x) for x in radii], str(curve),
-                         list(map(int, candidates)), int(buckets), str(device)]).encode())
+                         list(map(int, candidates)), list(map(int, stages)), list(map(str, fills)), int(buckets),
+                         int(budget), str(device)]).encode())
     return h.hexdigest()[:32]
 
 
@@ -55,18 +67,24 @@ def _time_step(plan: BatchPlan, repeats: int) -> float:
     return float(np.median(ts))
 
 
-def tune_leaf(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, buckets: int = 4, repeats: int = 2,
-              cache_path: str | None = None, log=None) -> dict:
-    """Returns {"leaf": per-cloud leaf sizes, "bucket": per-cloud group,
-    "mu": per-cloud mean neighbour count, "table": {group: {leaf: ms}},
-    "cached": bool}."""
+def record_bytes(sizes) -> int:
+    """Workspace the recorded fill needs for clouds of these sizes."""
+    return sum((int(n) + 63) // 64 for n in sizes) * RECORD_BYTES_PER_GROUP
+
+
+def tune(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, stages=STAGES, fills=FILLS,
+         buckets: int = 4, repeats: int = 2, record_budget: int = DEFAULT_RECORD_BUDGET,
+         cache_path: str | None = None, log=None) -> dict:
+    """Returns {"leaf", "stage", "record": per-cloud choices, "bucket": per-cloud
+    group, "mu": per-cloud mean neighbour count, "table": {group: {"leaf=L":
+    ms, "leaf=L/stage=S/fill=F": ms}}, "edges", "cached": bool}."""
     import torch
     sizes = [int(x) for x in sizes]
     nb = len(sizes)
     kernels = kernel if isinstance(kernel, (list, tuple)) else [kernel] * nb
     radii = r if isinstance(r, (list, tuple)) else [r] * nb
     device = torch.cuda.get_device_name(0)
-    key = _key(sizes, kernels, radii, curve, candidates, buckets, device)
+    key = _key(sizes, kernels, radii, curve, candidates, stages, fills, buckets, record_budget, device)
     path = cache_path or default_cache_path()
     try:
         with open(path) as f:
@@ -89,7 +107,7 @@ def tune_leaf(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, buc
     nbk = max(1, min(int(buckets), nb))
     edges = np.quantile(mu, np.linspace(0, 1, nbk + 1)[1:-1]) if nbk > 1 else np.array([])
     group = np.searchsorted(edges, mu, side="right") if nbk > 1 else np.zeros(nb, np.int64)
-    # 3. time every group with every candidate
+    # 3. per group: the leaf at the default tile, then the tile at that leaf
     table = {}
     best = {}
     for g in range(nbk):
@@ -97,21 +115,42 @@ def tune_leaf(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, buc
         if not members:
             continue
         sub = torch.cat([xyz[starts[c]:starts[c + 1]] for c in members])
-        ms = {}
-        for leaf in candidates:
-            plan = BatchPlan(sub, [sizes[c] for c in members], curve, 21, int(leaf), [kernels[c] for c in members],
-                             [radii[c] for c in members])
-            ms[int(leaf)] = _time_step(plan, repeats)
+        msz = [sizes[c] for c in members]
+        mk = [kernels[c] for c in members]
+        mr = [radii[c] for c in members]
+
+        def timed(leaf, stage, fill):
+            plan = BatchPlan(sub, msz, curve, 21, int(leaf), mk, mr, record=(fill == "record"), stage=int(stage))
+            ms = _time_step(plan, repeats)
             del plan
+            torch.cuda.empty_cache()
             if log:
                 log(f"[autotune] group {g} ({len(members)} clouds, mu {mu[members].min():.1f}-"
-                    f"{mu[members].max():.1f}): leaf {leaf} {ms[int(leaf)]:.2f} ms")
+                    f"{mu[members].max():.1f}): leaf {leaf} stage {stage} {fill} fill {ms:.2f} ms")
+            return ms
+
+        ms = {}
+        by_leaf = {}
+        for leaf in candidates:
+            by_leaf[int(leaf)] = ms[f"leaf={int(leaf)}"] = timed(leaf, 128, "search")
+        leaf = min(by_leaf, key=by_leaf.get)
+        tiles = {(128, "search"): by_leaf[leaf]}
+        fits = record_bytes(msz) <= record_budget
+        for stage in stages:
+            for fill in fills:
+                if (int(stage), fill) in tiles or (fill == "record" and not fits):
+                    continue
+                tiles[(int(stage), fill)] = timed(leaf, stage, fill)
+        for (stage, fill), v in tiles.items():
+            ms[f"leaf={leaf}/stage={stage}/fill={fill}"] = v
+        stage, fill = min(tiles, key=tiles.get)
         table[g] = ms
-        best[g] = min(ms, key=ms.get)
-    fallback = min(candidates)
-    leaf = [int(best.get(int(group[c]), fallback)) for c in range(nb)]
-    out = {"leaf": leaf, "bucket": [int(x) for x in group], "mu": [float(x) for x in mu],
-           "table": {str(g): {str(k): v for k, v in ms.items()} for g, ms in table.items()},
+        best[g] = (leaf, stage, fill)
+    fallback = (min(candidates), 128, "search")
+    choice = [best.get(int(group[c]), fallback) for c in range(nb)]
+    out = {"leaf": [int(x[0]) for x in choice], "stage": [int(x[1]) for x in choice],
+           "record": [x[2] == "record" for x in choice], "bucket": [int(x) for x in group],
+           "mu": [float(x) for x in mu], "table": {str(g): t for g, t in table.items()},
            "edges": [float(x) for x in edges]}
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

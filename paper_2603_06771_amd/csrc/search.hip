@@ -190,6 +190,7 @@ struct Query {
 
 // Shared LDS of one wave: traversal stack, candidate nodes, staged points.
 struct WaveLds {
+    static constexpr int kPts = kStage;
     int stack[kStack];
     int cand[kCand];         // candidate nodes (indices)
     uint32_t cbeg[kCand];    // their point ranges
@@ -380,7 +381,7 @@ __device__ __forceinline__ void stage_rounds(WaveLds &L, const float4 *__restric
             L.owner[at] = static_cast<uint8_t>(lo);
         }
         kept += static_cast<uint32_t>(__popcll(km));
-        if (kept > static_cast<uint32_t>(kStage - kWave) || (base + kWave >= total && kept > 0)) {
+        if (kept > static_cast<uint32_t>(WaveLds::kPts - kWave) || (base + kWave >= total && kept > 0)) {
             wave_sync();
             body(kept);
             wave_sync();
@@ -406,7 +407,9 @@ struct SearchCloud {
     float r;
     int32_t kernel;
     int32_t k;
-    int32_t pad;
+    int32_t stage;  // radius search: points staged per round (64, 128, 256)
+    int32_t rec;    // radius search: the cloud's hits are recorded (SFC_RECORD_HITS or the cloud's choice)
+    int64_t rg0;    // its groups' record regions start here (regions exist only for recording clouds)
 };
 
 struct SearchArgs {
@@ -490,11 +493,19 @@ __device__ __forceinline__ SearchCloud group_cloud(const SearchArgs &a, int64_t 
 // node is contained gets "true" for each of its points, by the same
 // argument, so no per-lane bookkeeping is needed).  Nodes contained for a
 // segment and mixed for none are counted without touching their points.
-struct RadLds {
+//
+// STAGE (points staged per round: 64, 128 or 256) is the search's tile: a
+// larger round amortises the per-round work (and, in the search fill, the
+// row flushes every round ends with) over more points, a smaller one needs
+// less LDS, so more waves stay resident.  It is chosen per cloud at run time
+// (the autotuner picks it per group of clouds); results do not depend on it.
+template <int STAGE>
+struct RadLdsT {
+    static constexpr int kPts = STAGE;
     int stack[kStack];
     int cand[kCand];         // candidate nodes (indices)
     uint32_t cbeg[kCand];    // their first points
-    float4 pts[kStage];
+    float4 pts[STAGE];
     union {
         uint32_t clen[kWave];   // sizes of the batch candidates (read before staging starts)
         uint32_t cincl[kWave];  // inclusive prefix of staged sizes of the batch
@@ -502,11 +513,15 @@ struct RadLds {
     float seg[kSegMax][6];
 };
 
-struct FillLds : RadLds {
+using RadLds = RadLdsT<kStage>;
+
+template <int STAGE>
+struct FillLdsT : RadLdsT<STAGE> {
     uint8_t rows[kWave * (kRowCap + 1)];   // per-query output staging: staged-point slots
     uint64_t fpos[kWave];                  // rows being flushed, by list entry: global position
     uint32_t fmeta[kWave];                 // and lane | entries that fit the row's slot << 8
 };
+using FillLds = FillLdsT<kStage>;
 
 // the range form also keeps the candidates' ends and records the candidate
 // of every staged point
@@ -622,7 +637,7 @@ __device__ __forceinline__ void stage_union(Lds &L, const float4 *__restrict__ p
             if constexpr (OWNER) L.owner[kept + rank_below(km)] = static_cast<uint8_t>(lo);
         }
         kept += static_cast<uint32_t>(__popcll(km));
-        if (kept > static_cast<uint32_t>(kStage - kWave) || (!carry && base + kWave >= total && kept > 0)) {
+        if (kept > static_cast<uint32_t>(Lds::kPts - kWave) || (!carry && base + kWave >= total && kept > 0)) {
             wave_sync();
             body(kept);
             wave_sync();
@@ -771,8 +786,9 @@ __device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, con
 // counted from its size), so the records hold every neighbour in the order
 // k_radius_fill would write them.  A group whose records do not fit kRecCap,
 // or that is deferred, is marked kRecOverflow and left to k_radius_fill.
-template <int KERNEL, bool REC>
-__device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
+template <int KERNEL, bool REC, int STAGE>
+__device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const SearchArgs &a, const SearchCloud &C,
+                                                  int64_t lg) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;  // position within the cloud's rows
     int64_t row;
@@ -809,8 +825,8 @@ __device__ __forceinline__ void radius_count_body(RadLds &L, const SearchArgs &a
         // t0 + j; per 64 points the ones with a neighbour are compacted and
         // stored (lane = record: coalesced)
         const float qx = q.valid ? q.x : INFINITY, qy = q.valid ? q.y : INFINITY, qz = q.valid ? q.z : INFINITY;
-        uint32_t *const ridx = a.rec_idx + gg * kRecCap;
-        uint64_t *const rmask = a.rec_mask + gg * kRecCap;
+        uint32_t *const ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
+        uint64_t *const rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
         auto body_rec = [&](uint32_t n_) {
             const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
             for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
@@ -957,8 +973,8 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
         }
         wave_sync();
     };
-    const uint32_t *ridx = a.rec_idx + gg * kRecCap;
-    const uint64_t *rmask = a.rec_mask + gg * kRecCap;
+    const uint32_t *ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
+    const uint64_t *rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
     // kRecBatch chunks of 64 records per round trip (lane = record of each chunk)
     for (uint32_t b0 = 0; b0 < n; b0 += kRecBatch * kWave) {
         uint32_t bpi[kRecBatch], blo[kRecBatch], bhi[kRecBatch];
@@ -1077,8 +1093,8 @@ __device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const S
         const uint32_t to_line = kRecLine - static_cast<uint32_t>(gpos & (kRecLine - 1));
         return nb >= to_line ? to_line : 0u;
     };
-    const uint32_t *ridx = a.rec_idx + gg * kRecCap;
-    const uint64_t *rmask = a.rec_mask + gg * kRecCap;
+    const uint32_t *ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
+    const uint64_t *rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
     uint32_t k = 0;  // batch number
     for (uint32_t b0 = 0; b0 < n; b0 += kRingHalf, ++k) {
         constexpr int kPer = kRingHalf / kWave;
@@ -1164,8 +1180,9 @@ __device__ __forceinline__ void fill_one(RadLds &L, const SearchCloud &C, float 
         });
 }
 
-template <int KERNEL>
-__device__ __forceinline__ void radius_fill_body(FillLds &L, const SearchArgs &a, const SearchCloud &C, int64_t lg) {
+template <int KERNEL, int STAGE>
+__device__ __forceinline__ void radius_fill_body(FillLdsT<STAGE> &L, const SearchArgs &a, const SearchCloud &C,
+                                                 int64_t lg) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
     int64_t row;
@@ -1432,25 +1449,44 @@ __device__ __forceinline__ bool records_valid(const SearchArgs &a) {
 
 }  // namespace
 
-// One wave per group of 64 queries of one cloud; the cloud's kernel selects
-// the (wave-uniform) body.
-__global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) {
-    __shared__ RadLds L;
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
-    const SearchCloud C = group_cloud(a, g);
-    const int64_t lg = g - C.g0;
+// The count and search-fill kernels take their LDS from the launch's dynamic
+// allocation, sized by the host for the largest staging tile among the
+// launch's clouds; each group views it with its own cloud's layout.
+extern __shared__ __align__(16) unsigned char g_radius_lds[];
+
+template <bool REC, int STAGE>
+__device__ __forceinline__ void radius_count_tile(const SearchArgs &a, const SearchCloud &C, int64_t lg) {
+    RadLdsT<STAGE> &L = *reinterpret_cast<RadLdsT<STAGE> *>(g_radius_lds);
     switch (C.kernel) {
-    case SFC_SPHERE: radius_count_body<SFC_SPHERE, false>(L, a, C, lg); break;
-    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE, false>(L, a, C, lg); break;
-    case SFC_CUBE: radius_count_body<SFC_CUBE, false>(L, a, C, lg); break;
-    default: radius_count_body<SFC_SQUARE, false>(L, a, C, lg); break;
+    case SFC_SPHERE: radius_count_body<SFC_SPHERE, REC, STAGE>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE, REC, STAGE>(L, a, C, lg); break;
+    case SFC_CUBE: radius_count_body<SFC_CUBE, REC, STAGE>(L, a, C, lg); break;
+    default: radius_count_body<SFC_SQUARE, REC, STAGE>(L, a, C, lg); break;
     }
 }
 
-// the count that also records every group's hits (SFC_RECORD_HITS)
+template <bool REC>
+__device__ __forceinline__ void radius_count_group(const SearchArgs &a, const SearchCloud &C, int64_t lg) {
+    switch (C.stage) {
+    case 64: radius_count_tile<REC, 64>(a, C, lg); break;
+    case 256: radius_count_tile<REC, 256>(a, C, lg); break;
+    default: radius_count_tile<REC, 128>(a, C, lg); break;
+    }
+}
+
+// One wave per group of 64 queries of one cloud; the cloud's kernel and
+// staging tile select the (wave-uniform) body.
+__global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) {
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const SearchCloud C = group_cloud(a, g);
+    radius_count_group<false>(a, C, g - C.g0);
+}
+
+// the count that also records the hits of every group of the recording
+// clouds (SFC_RECORD_HITS, or the cloud's own choice in a batch); groups of
+// the other clouds are counted plainly and left to k_radius_fill
 __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
-    __shared__ RadLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (g == 0 && lane_id() == 0) {  // the records' provenance (read by the fills, which run after this kernel)
@@ -1458,12 +1494,11 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
         a.rec_tag[1] = a.tag1;
     }
     const SearchCloud C = group_cloud(a, g);
-    const int64_t lg = g - C.g0;
-    switch (C.kernel) {
-    case SFC_SPHERE: radius_count_body<SFC_SPHERE, true>(L, a, C, lg); break;
-    case SFC_CIRCLE: radius_count_body<SFC_CIRCLE, true>(L, a, C, lg); break;
-    case SFC_CUBE: radius_count_body<SFC_CUBE, true>(L, a, C, lg); break;
-    default: radius_count_body<SFC_SQUARE, true>(L, a, C, lg); break;
+    if (C.rec) {
+        radius_count_group<true>(a, C, g - C.g0);
+    } else {
+        if (lane_id() == 0) a.rec_n[g] = kRecOverflow;
+        radius_count_group<false>(a, C, g - C.g0);
     }
 }
 
@@ -1496,19 +1531,28 @@ __global__ __launch_bounds__(64) void k_radius_fill_rec_long(SearchArgs a) {
     radius_fill_rec_long_body(L, a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
 }
 
+template <int STAGE>
+__device__ __forceinline__ void radius_fill_tile(const SearchArgs &a, const SearchCloud &C, int64_t lg) {
+    FillLdsT<STAGE> &L = *reinterpret_cast<FillLdsT<STAGE> *>(g_radius_lds);
+    switch (C.kernel) {
+    case SFC_SPHERE: radius_fill_body<SFC_SPHERE, STAGE>(L, a, C, lg); break;
+    case SFC_CIRCLE: radius_fill_body<SFC_CIRCLE, STAGE>(L, a, C, lg); break;
+    case SFC_CUBE: radius_fill_body<SFC_CUBE, STAGE>(L, a, C, lg); break;
+    default: radius_fill_body<SFC_SQUARE, STAGE>(L, a, C, lg); break;
+    }
+}
+
 __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
-    __shared__ FillLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
     if (a.rec_n && records_valid(a) && a.rec_n[g] != kRecOverflow) return;  // written from its records
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
-    switch (C.kernel) {
-    case SFC_SPHERE: radius_fill_body<SFC_SPHERE>(L, a, C, lg); break;
-    case SFC_CIRCLE: radius_fill_body<SFC_CIRCLE>(L, a, C, lg); break;
-    case SFC_CUBE: radius_fill_body<SFC_CUBE>(L, a, C, lg); break;
-    default: radius_fill_body<SFC_SQUARE>(L, a, C, lg); break;
+    switch (C.stage) {
+    case 64: radius_fill_tile<64>(a, C, lg); break;
+    case 256: radius_fill_tile<256>(a, C, lg); break;
+    default: radius_fill_tile<128>(a, C, lg); break;
     }
 }
 
@@ -2016,20 +2060,23 @@ SearchCloud cloud_entry(const sfc_octree &t, int64_t q_offset, int64_t nq, int64
     c.r = r;
     c.kernel = kernel;
     c.k = k;
-    c.pad = 0;
+    c.stage = kStage;
+    c.rec = 0;
+    c.rg0 = 0;
     return c;
 }
 
 // Validates a batch for search and builds its host table; returns the total
 // group count, or -1 (error set) if the batch is malformed.
 int64_t search_table(const char *who, int B, const sfc_cloud *clouds, const float *queries, int64_t nq_total,
-                     bool knn, int kstride, std::vector<SearchCloud> &tab) {
+                     bool knn, int kstride, std::vector<SearchCloud> &tab, uint32_t flags = 0,
+                     int64_t *rec_groups = nullptr) {
     if (B < 1 || B > (1 << 20) || !clouds || nq_total < 0) {
         set_error("%s: invalid batch", who);
         return -1;
     }
     tab.resize(B);
-    int64_t rows = 0, g = 0;
+    int64_t rows = 0, g = 0, rg = 0;
     for (int c = 0; c < B; ++c) {
         const sfc_cloud &C = clouds[c];
         const bool kernel_ok = knn ? (C.k >= 1 && C.k <= kstride) : (C.kernel >= 0 && C.kernel <= 3);
@@ -2039,10 +2086,21 @@ int64_t search_table(const char *who, int B, const sfc_cloud *clouds, const floa
                       "q_offset == offset)", who, c);
             return -1;
         }
+        if (!knn && C.stage != 0 && C.stage != 64 && C.stage != 128 && C.stage != 256) {
+            set_error("%s: cloud %d: stage %u is not 0, 64, 128 or 256", who, c, C.stage);
+            return -1;
+        }
         tab[c] = cloud_entry(C.tree, C.q_offset, C.nq, g, C.kernel, C.r, C.k);
+        if (!knn) {
+            tab[c].stage = C.stage ? static_cast<int32_t>(C.stage) : kStage;
+            tab[c].rec = ((flags & SFC_RECORD_HITS) || C.record) ? 1 : 0;
+            tab[c].rg0 = rg;
+            if (tab[c].rec) rg += (C.nq + kWave - 1) / kWave;
+        }
         rows += C.nq;
         g += (C.nq + kWave - 1) / kWave;
     }
+    if (rec_groups) *rec_groups = rg;
     if (rows != nq_total) {
         set_error("%s: nq_total %lld differs from the sum of the clouds' nq (%lld)", who, (long long)nq_total,
                   (long long)rows);
@@ -2100,7 +2158,9 @@ bool wants_order(const float *queries, int64_t nq_total, uint32_t flags) {
     return queries && !(flags & SFC_QUERIES_ORDERED) && nq_total > kWave;
 }
 
-size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem, SearchWs *w, bool record = false) {
+// rec_groups: record regions (groups of the recording clouds); 0: no records
+size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem, SearchWs *w,
+                       int64_t rec_groups = 0) {
     Carver c(mem);
     SearchWs x;
     if (B > 1) x.tab = c.take<SearchCloud>(B);
@@ -2116,10 +2176,10 @@ size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem
         x.radix = c.take<char>(radix_ws_bytes(nq_total));
         x.starts = c.take<int64_t>(B + 1);
     }
-    if (record) {
+    if (rec_groups > 0) {
         const int64_t groups = nq_total / kWave + B + 1;
-        x.rec_idx = c.take<uint32_t>(groups * kRecCap);
-        x.rec_mask = c.take<uint64_t>(groups * kRecCap);
+        x.rec_idx = c.take<uint32_t>(rec_groups * kRecCap);
+        x.rec_mask = c.take<uint64_t>(rec_groups * kRecCap);
         x.rec_n = c.take<uint32_t>(groups);
         x.rec_tag = c.take<uint64_t>(2);
     }
@@ -2128,8 +2188,26 @@ size_t carve_search_ws(int B, int64_t nq_total, bool scan, bool order, void *mem
     return c.bytes();
 }
 
-size_t search_ws_bytes(int B, int64_t nq_total, bool scan, bool order = false, bool record = false) {
-    return carve_search_ws(B, nq_total, scan, order, nullptr, nullptr, record);
+size_t search_ws_bytes(int B, int64_t nq_total, bool scan, bool order = false, int64_t rec_groups = 0) {
+    return carve_search_ws(B, nq_total, scan, order, nullptr, nullptr, rec_groups);
+}
+
+// record regions a launch needs: the groups of its recording clouds
+int64_t record_groups(const std::vector<SearchCloud> &tab) {
+    int64_t rg = 0;
+    for (const SearchCloud &c : tab)
+        if (c.rec) rg += (c.nq + kWave - 1) / kWave;
+    return rg;
+}
+
+// dynamic LDS of the count and search-fill kernels: the layout of the
+// largest staging tile among the launch's clouds
+size_t radius_lds_bytes(const std::vector<SearchCloud> &tab, bool fill) {
+    int st = 64;
+    for (const SearchCloud &c : tab) st = std::max(st, static_cast<int>(c.stage));
+    if (st > 128) return fill ? sizeof(FillLdsT<256>) : sizeof(RadLdsT<256>);
+    if (st > 64) return fill ? sizeof(FillLdsT<128>) : sizeof(RadLdsT<128>);
+    return fill ? sizeof(FillLdsT<64>) : sizeof(RadLdsT<64>);
 }
 
 // Sorts the external queries of every cloud by their code (stable, so equal
@@ -2195,9 +2273,10 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
                   void *ws, hipStream_t s) {
     const int B = static_cast<int>(tab.size());
     const bool order = wants_order(a.queries, a.nq_total, a.flags);
-    const bool record = (a.flags & SFC_RECORD_HITS) != 0;
+    const int64_t rec_groups = record_groups(tab);
+    const bool record = rec_groups > 0;
     SearchWs w;
-    carve_search_ws(B, a.nq_total, true, order, ws, &w, record);
+    carve_search_ws(B, a.nq_total, true, order, ws, &w, rec_groups);
     if (record) {
         a.rec_idx = w.rec_idx;
         a.rec_mask = w.rec_mask;
@@ -2229,11 +2308,12 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
                 k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
                 SFC_LAUNCH_CHECK("k_reset_spread");
             }
+            const size_t lds = radius_lds_bytes(tab, false);
             if (record) {
-                k_radius_count_rec<<<grid, 64, 0, s>>>(a);
+                k_radius_count_rec<<<grid, 64, lds, s>>>(a);
                 SFC_LAUNCH_CHECK("k_radius_count_rec");
             } else {
-                k_radius_count<<<grid, 64, 0, s>>>(a);
+                k_radius_count<<<grid, 64, lds, s>>>(a);
                 SFC_LAUNCH_CHECK("k_radius_count");
             }
             if (a.queries) {  // only external queries are ever deferred
@@ -2255,7 +2335,7 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
             k_radius_fill_rec_long<<<grid, 64, 0, s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_fill_rec_long");
         }
-        k_radius_fill<<<grid, 64, 0, s>>>(a);
+        k_radius_fill<<<grid, 64, radius_lds_bytes(tab, true), s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");
         if (a.queries) {
             k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
@@ -2330,7 +2410,12 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         set_error("radius_search: invalid argument");
         return SFC_EINVAL;
     }
-    const size_t need = search_ws_bytes(1, nq, true, wants_order(queries, nq, flags), (flags & SFC_RECORD_HITS) != 0);
+    if ((flags & SFC_STAGE_MASK) == SFC_STAGE_MASK) {
+        set_error("radius_search: flags select no staging tile");
+        return SFC_EINVAL;
+    }
+    const size_t need = search_ws_bytes(1, nq, true, wants_order(queries, nq, flags),
+                                        (flags & SFC_RECORD_HITS) ? (nq + kWave - 1) / kWave : 0);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;
@@ -2348,6 +2433,8 @@ extern "C" int radius_search(const sfc_octree *tree, const float *queries, int64
         return SFC_OK;
     }
     std::vector<SearchCloud> tab(1, cloud_entry(*tree, 0, nq, 0, kernel, r, 0));
+    tab[0].stage = (flags & SFC_STAGE_64) ? 64 : ((flags & SFC_STAGE_256) ? 256 : kStage);
+    tab[0].rec = (flags & SFC_RECORD_HITS) ? 1 : 0;
     SearchArgs a = blank_args();
     a.queries = queries;
     a.flags = flags;
@@ -2438,10 +2525,11 @@ extern "C" int radius_search_batched(int B, const sfc_cloud *clouds, const float
         return SFC_EINVAL;
     }
     std::vector<SearchCloud> tab;
-    const int64_t groups = search_table("radius_search_batched", B, clouds, queries, nq_total, false, 0, tab);
+    int64_t rec_groups = 0;
+    const int64_t groups =
+        search_table("radius_search_batched", B, clouds, queries, nq_total, false, 0, tab, flags, &rec_groups);
     if (groups < 0) return SFC_EINVAL;
-    const size_t need =
-        search_ws_bytes(B, nq_total, true, wants_order(queries, nq_total, flags), (flags & SFC_RECORD_HITS) != 0);
+    const size_t need = search_ws_bytes(B, nq_total, true, wants_order(queries, nq_total, flags), rec_groups);
     if (!ws) {
         *ws_bytes = need;
         return SFC_OK;

@@ -23,11 +23,12 @@ class BatchPlan:
     points are its queries."""
 
     def __init__(self, xyz, sizes, curve="hilbert", bits=21, leaf_size=32, kernel="sphere", r=1.0, k=None,
-                 capacity: int | None = None, record: bool = False):
+                 capacity: int | None = None, record=False, stage=128):
         torch = _torch()
-        # record: the count pass records every group's hits and the fill
-        # writes the rows from them (SFC_RECORD_HITS; larger workspace)
-        self.flags = B.RECORD_HITS if (record and k is None) else 0
+        # record (one value or one per cloud): the count pass records the
+        # cloud's hits and the fill writes its rows from them (larger
+        # workspace); stage (one value or one per cloud): the staging tile
+        self.flags = 0
         self.L = B.load()
         self.xyz = _xyz(torch, xyz)
         self.sizes = [int(x) for x in sizes]
@@ -43,6 +44,8 @@ class BatchPlan:
         kernels = _per_cloud(kernel, nb, "kernel")
         radii = _per_cloud(r, nb, "r")
         ks = _per_cloud(k if k is not None else 1, nb, "k")
+        records = _per_cloud(record, nb, "record")
+        stages = _per_cloud(stage, nb, "stage")
         cl = (B.SfcCloud * nb)()
         off = 0
         for c in range(nb):
@@ -56,6 +59,10 @@ class BatchPlan:
             cl[c].k = int(ks[c])
             cl[c].q_offset = off
             cl[c].nq = self.sizes[c]
+            if int(stages[c]) not in (64, 128, 256):
+                raise ValueError(f"stage must be 64, 128 or 256, not {stages[c]!r}")
+            cl[c].stage = int(stages[c])
+            cl[c].record = 1 if (records[c] and k is None) else 0
             off += self.sizes[c]
         self.clouds = cl
         tb = ctypes.c_size_t(0)

@@ -109,6 +109,35 @@ def test_batch_radius_cloud_queries(sfc):
     assert q0 == c.size
 
 
+def test_batch_radius_per_cloud_tile_and_record(sfc):
+    """Per-cloud staging tiles and per-cloud recorded fills in one launch
+    give the rows of the default batch (same order inside every row), and
+    each cloud matches the oracle."""
+    import torch
+    batch, clouds = _mixed_batch(sfc)
+    stages = [64, 256, 128, 256, 64, 128, 256, 64]
+    records = [True, False, True, True, False, True, False, True]
+    announce("batch radius, per-cloud staging tiles and recorded fills")
+    ref = sfc.radius_search_batched(batch, None, None, KERN, RADII)
+    got = sfc.radius_search_batched(batch, None, None, KERN, RADII, record=records, stage=stages)
+    total = int(ref[1][-1])
+    cap = sfc.radius_search_batched(batch, None, None, KERN, RADII, capacity=total, record=records, stage=stages)
+    torch.cuda.synchronize()
+    for x, y, name in zip(ref, got, ("counts", "offsets", "indices")):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), f"{name} differ"
+    for x, y, name in zip(ref[:2], cap[:2], ("counts", "offsets")):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), f"one call: {name} differ"
+    assert np.array_equal(ref[2].cpu().numpy()[:total], cap[2].cpu().numpy()[:total]), "one call: indices differ"
+    c, o, i = (x.cpu().numpy() for x in got)
+    q0 = 0
+    for cl, pts in enumerate(clouds):
+        n = pts.shape[0]
+        perm = batch.tree(cl).perm().cpu().numpy().view(np.uint32)
+        ref_cl = oracle.radius_search(pts, pts[perm], KERN[cl], RADII[cl])
+        assert_csr_equal(_rows(c, o, i, q0, n), ref_cl, f"cloud {cl} stage {stages[cl]} record {records[cl]}")
+        q0 += n
+
+
 def test_batch_radius_external_queries(sfc):
     import torch
     batch, clouds = _mixed_batch(sfc)

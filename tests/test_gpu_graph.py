@@ -1,6 +1,7 @@
 """Pre-allocated batched plans replayed from a HIP graph: every replay (with
 eager work and synchronisations between replays) must reproduce the eager
-result, which itself matches the oracle; and the leaf-size autotuner."""
+result, which itself matches the oracle; and the autotuner of leaf size,
+staging tile and fill."""
 import numpy as np
 import pytest
 
@@ -96,17 +97,43 @@ def test_knn_plan_graph_replays():
         assert np.array_equal(plan.d2.cpu().numpy().view(np.uint32), gd.view(np.uint32))
 
 
-def test_autotune_leaf(tmp_path):
+def test_autotune_leaf_tile_fill(tmp_path):
+    """The tuner picks (leaf, staging tile, fill) per group of clouds from the
+    candidates, caches the choice, and a plan built with its per-cloud choices
+    gives the same rows as the default plan."""
+    import torch
     from paper_2603_06771_amd import autotune
+    from paper_2603_06771_amd.plan import BatchPlan
     clouds = _clouds()
     xyz = _dev(np.concatenate(clouds))
     path = str(tmp_path / "tune.json")
     announce("autotune")
-    t = autotune.tune_leaf(xyz, SIZES, KERN, RADII, "hilbert", candidates=(8, 32), buckets=2, repeats=1,
-                           cache_path=path)
-    assert not t["cached"] and len(t["leaf"]) == len(SIZES)
-    assert set(t["leaf"]) <= {8, 32}
-    assert all(len(v) == 2 for v in t["table"].values())
-    t2 = autotune.tune_leaf(xyz, SIZES, KERN, RADII, "hilbert", candidates=(8, 32), buckets=2, repeats=1,
-                            cache_path=path)
-    assert t2["cached"] and t2["leaf"] == t["leaf"]
+    kw = dict(candidates=(8, 32), stages=(64, 256), buckets=2, repeats=1, cache_path=path)
+    t = autotune.tune(xyz, SIZES, KERN, RADII, "hilbert", **kw)
+    assert not t["cached"] and len(t["leaf"]) == len(SIZES) == len(t["stage"]) == len(t["record"])
+    assert set(t["leaf"]) <= {8, 32} and set(t["stage"]) <= {64, 128, 256}
+    for g, ms in t["table"].items():
+        assert sum(k.startswith("leaf=") and "/" not in k for k in ms) == 2
+        # the default tile at the chosen leaf, then stage x fill (64 and 256, search and record)
+        assert sum("/" in k for k in ms) == 5
+    t2 = autotune.tune(xyz, SIZES, KERN, RADII, "hilbert", **kw)
+    assert t2["cached"] and (t2["leaf"], t2["stage"], t2["record"]) == (t["leaf"], t["stage"], t["record"])
+    # a zero record budget keeps every group on the search fill
+    t3 = autotune.tune(xyz, SIZES, KERN, RADII, "hilbert", record_budget=0, **kw)
+    assert not any(t3["record"]) and all("fill=record" not in k for ms in t3["table"].values() for k in ms)
+    # the tuned plan gives the rows of the default plan
+    announce("autotune: tuned plan against the default plan")
+    ref = BatchPlan(xyz, SIZES, "hilbert", 21, LEAF, KERN, RADII)
+    ref.run()
+    tuned = BatchPlan(xyz, SIZES, "hilbert", 21, t["leaf"], KERN, RADII, record=t["record"], stage=t["stage"])
+    tuned.run()
+    torch.cuda.synchronize()
+    rc, ro, ri = _csr(ref)
+    c, o, i = _csr(tuned)
+    assert np.array_equal(c, rc) and np.array_equal(o, ro)
+    # leaf sizes change the stored order (rows keep the query's position; the
+    # order inside a row may differ): compare the row sets
+    rows = np.repeat(np.arange(c.size), c)
+    a = i[:o[-1]][np.lexsort((i[:o[-1]], rows))]
+    b = ri[:ro[-1]][np.lexsort((ri[:ro[-1]], rows))]
+    assert np.array_equal(a, b)

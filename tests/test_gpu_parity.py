@@ -311,3 +311,30 @@ def test_knn_external_and_padding(sfc):
     announce("knn k > n")
     small = _cloud("uniform", 11, seed=3)
     _knn_case(sfc, small, "hilbert", 4, 32)
+
+
+@pytest.mark.parametrize("stage", [64, 256])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_radius_staging_tiles(sfc, stage, kernel):
+    """Every staging tile gives the oracle's sets, and the same rows in the
+    same order as the default tile (count + search fill, and recorded hits),
+    for cloud queries and for external queries the call sorts."""
+    import torch
+    pts = datagen.lidar_tile(50021, seed=31)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(32)
+    ext = (pts[rng.choice(pts.shape[0], 7001, replace=False)] + rng.normal(0, 0.3, (7001, 3))).astype(np.float32)
+    for queries, qpts in ((None, pts[perm]), (ext, ext)):
+        for r in (0.5, 2.5):
+            for record in (False, True):
+                announce(f"staging tile {stage} {kernel} r={r} record={record} external={queries is not None}")
+                q = None if queries is None else _dev(queries)
+                ref = sfc.radius_search(t, q, kernel, r, record=record)
+                got = sfc.radius_search(t, q, kernel, r, record=record, stage=stage)
+                torch.cuda.synchronize()
+                for x, y, name in zip(ref, got, ("counts", "offsets", "indices")):
+                    assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), f"{name} differ from stage 128"
+                if not record:
+                    assert_csr_equal(tuple(x.cpu().numpy() for x in got), oracle.radius_search(pts, qpts, kernel, r),
+                                     f"stage {stage} {kernel} r={r}")
