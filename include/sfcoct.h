@@ -307,6 +307,24 @@ int octree_batch_layout(int B, sfc_cloud *clouds, void *tree_mem, size_t *bytes)
 int build_linear_octree_batched(const float *xyz, int B, const sfc_cloud *clouds, void *ws, size_t *ws_bytes,
                                 void *stream);
 
+/* Memory accounting of Section 7.5 (Tables 6-7: a linear octree costs a few
+ * percent of the cloud): the trees of a batch built by
+ * build_linear_octree_batched, copied into a block of exactly the memory
+ * their actual node and leaf counts need, instead of the upper bounds that
+ * octree_batch_layout reserves so the build never waits for the host (at
+ * leaf size 64 the bound is about 24 times the actual internal nodes).
+ * Waits for `stream` and reads every tree's sfc_tree_info (the host blocks).
+ * With dst_mem == NULL only *bytes is set.  Otherwise dst_mem (device,
+ * 256-byte aligned, at least *bytes, not overlapping the source) receives
+ * the shared point, code and permutation arrays and every tree's frame,
+ * info and node arrays, asynchronously on `stream`, and out[0..B) the same
+ * descriptors as clouds with `tree` viewing dst_mem (max_nodes / max_leaves
+ * = the actual counts).  The source memory can be freed once the copies
+ * are done; searches on the copies give the same results.  SFC_EINVAL if a
+ * tree was not built (or not laid out by octree_batch_layout). */
+int octree_batch_compact(int B, const sfc_cloud *clouds, void *dst_mem, size_t *bytes, sfc_cloud *out,
+                         void *stream);
+
 /* Radius search for every cloud of the batch with its own kernel and radius,
  * in one launch per pass.  queries: concatenated per-cloud query blocks
  * (cloud c at rows [q_offset_c, q_offset_c + nq_c)), or NULL (each cloud's own

@@ -24,7 +24,7 @@ STAGE_FLAGS = {64: STAGE_64, 128: 0, 256: STAGE_256}
 EXPORTS = ("encode_sfc", "octree_bytes", "build_linear_octree", "radius_search", "knn_search",
            "octree_batch_layout", "build_linear_octree_batched", "radius_search_batched", "knn_search_batched",
            "radius_search_struct", "knn_locality", "gather_points", "radius_search_check",
-           "radius_search_noalloc", "sfc_last_error", "sfc_version")
+           "radius_search_noalloc", "octree_batch_compact", "sfc_last_error", "sfc_version")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
                                        P, ctypes.POINTER(SZ), P]
     L.knn_locality.argtypes = [ctypes.POINTER(SfcOctree), P, I64, P, I32, I32, P, P, P, ctypes.POINTER(SZ), P]
     L.radius_search_check.argtypes = [P, I64, U64, ctypes.POINTER(U64), P]
+    L.octree_batch_compact.argtypes = [I32, ctypes.POINTER(SfcCloud), P, ctypes.POINTER(SZ), ctypes.POINTER(SfcCloud),
+                                       P]
     L.radius_search_noalloc.argtypes = [ctypes.POINTER(SfcOctree), P, I64, I32, F32, P, P, P, U64, U32, P]
     L.sfc_last_error.restype = ctypes.c_char_p
     L.sfc_version.restype = ctypes.c_char_p

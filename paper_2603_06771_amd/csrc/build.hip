@@ -709,7 +709,104 @@ static bool clouds_valid(int B, const sfc_cloud *cl) {
     return expect <= 0xFFFFFFFFll;
 }
 
+// The layout of batch_layout with the actual counts of every tree (nodes
+// and leaves from its sfc_tree_info) instead of the upper bounds: shared
+// point arrays first, then each cloud's frame, info and node arrays.
+static size_t compact_layout(int B, const sfc_cloud *src, const sfc_tree_info *info, sfc_cloud *dst, void *mem) {
+    int64_t total = 0;
+    for (int c = 0; c < B; ++c) total = std::max<int64_t>(total, src[c].offset + src[c].n);
+    Carver cv(mem);
+    float *points = cv.take<float>(4 * static_cast<size_t>(total));
+    uint64_t *keys = cv.take<uint64_t>(total);
+    uint32_t *perm = cv.take<uint32_t>(total);
+    for (int c = 0; c < B; ++c) {
+        const int64_t nl = info[c].n_leaves, nn = info[c].n_nodes;
+        sfc_octree t = src[c].tree;
+        t.frame = cv.take<sfc_frame>(1);
+        t.info = cv.take<sfc_tree_info>(1);
+        t.leaves = cv.take<uint64_t>(nl + 1);
+        t.counts = cv.take<uint32_t>(nl);
+        t.nodes = cv.take<sfc_node>(nn);
+        t.child = cv.take<int32_t>(nn);
+        t.node_key = cv.take<uint64_t>(nn);
+        t.node_level = cv.take<uint8_t>(nn);
+        t.points = points ? points + 4 * src[c].offset : nullptr;
+        t.keys = keys ? keys + src[c].offset : nullptr;
+        t.perm = perm ? perm + src[c].offset : nullptr;
+        t.max_nodes = nn;
+        t.max_leaves = nl;
+        if (dst) {
+            dst[c] = src[c];
+            dst[c].tree = t;
+        }
+    }
+    return cv.bytes();
+}
+
 }  // namespace sfc
+
+extern "C" int octree_batch_compact(int B, const sfc_cloud *clouds, void *dst_mem, size_t *bytes, sfc_cloud *out,
+                                    void *stream) {
+    using namespace sfc;
+    if (!bytes || !clouds_valid(B, clouds) || (dst_mem && !out)) {
+        set_error("octree_batch_compact: invalid argument");
+        return SFC_EINVAL;
+    }
+    for (int c = 0; c < B; ++c)
+        if (!clouds[c].tree.info || !clouds[c].tree.nodes || !clouds[c].tree.keys ||
+            clouds[c].tree.keys - clouds[c].offset != clouds[0].tree.keys - clouds[0].offset) {
+            set_error("octree_batch_compact: trees not laid out by octree_batch_layout");
+            return SFC_EINVAL;
+        }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the actual counts (the host waits for the build on the stream)
+    std::vector<sfc_tree_info> info(B);
+    for (int c = 0; c < B; ++c)
+        SFC_HIP_TRY(hipMemcpyAsync(&info[c], clouds[c].tree.info, sizeof(sfc_tree_info), hipMemcpyDeviceToHost, s));
+    SFC_HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < B; ++c)
+        if (info[c].status != 0 || info[c].n_nodes < 1 || info[c].n_nodes > clouds[c].tree.max_nodes ||
+            info[c].n_leaves < 1 || info[c].n_leaves > clouds[c].tree.max_leaves) {
+            set_error("octree_batch_compact: cloud %d: its tree is not built (status %d, %lld nodes)", c,
+                      info[c].status, static_cast<long long>(info[c].n_nodes));
+            return SFC_EINVAL;
+        }
+    const size_t need = compact_layout(B, clouds, info.data(), nullptr, nullptr);
+    if (!dst_mem) {
+        *bytes = need;
+        return SFC_OK;
+    }
+    if (*bytes < need || (reinterpret_cast<uintptr_t>(dst_mem) & 255u)) {
+        set_error("octree_batch_compact: destination needs %zu bytes, 256-aligned", need);
+        return SFC_EINVAL;
+    }
+    compact_layout(B, clouds, info.data(), out, dst_mem);
+    int64_t total = 0;
+    for (int c = 0; c < B; ++c) total = std::max<int64_t>(total, clouds[c].offset + clouds[c].n);
+    auto copy = [&](void *d, const void *src, size_t n) -> int {
+        if (n == 0) return SFC_OK;
+        SFC_HIP_TRY(hipMemcpyAsync(d, src, n, hipMemcpyDeviceToDevice, s));
+        return SFC_OK;
+    };
+    const sfc_octree &a0 = clouds[0].tree, &b0 = out[0].tree;
+    const int64_t o0 = clouds[0].offset;
+    int rc = copy(b0.points - 4 * o0, a0.points - 4 * o0, 16 * static_cast<size_t>(total));
+    if (!rc) rc = copy(b0.keys - o0, a0.keys - o0, 8 * static_cast<size_t>(total));
+    if (!rc) rc = copy(b0.perm - o0, a0.perm - o0, 4 * static_cast<size_t>(total));
+    for (int c = 0; c < B && !rc; ++c) {
+        const sfc_octree &a = clouds[c].tree, &b = out[c].tree;
+        const size_t nl = static_cast<size_t>(info[c].n_leaves), nn = static_cast<size_t>(info[c].n_nodes);
+        rc = copy(b.frame, a.frame, sizeof(sfc_frame));
+        if (!rc) rc = copy(b.info, a.info, sizeof(sfc_tree_info));
+        if (!rc) rc = copy(b.leaves, a.leaves, 8 * (nl + 1));
+        if (!rc) rc = copy(b.counts, a.counts, 4 * nl);
+        if (!rc) rc = copy(b.nodes, a.nodes, sizeof(sfc_node) * nn);
+        if (!rc) rc = copy(b.child, a.child, 4 * nn);
+        if (!rc) rc = copy(b.node_key, a.node_key, 8 * nn);
+        if (!rc) rc = copy(b.node_level, a.node_level, nn);
+    }
+    return rc;
+}
 
 extern "C" int octree_bytes(int64_t n, uint32_t leaf_size, int bits, size_t *bytes) {
     using namespace sfc;

@@ -1502,33 +1502,24 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
     }
 }
 
-// rows of the recorded groups in the short-row form; the others are left to
-// k_radius_fill_rec_long and (records that did not fit) k_radius_fill
+// rows of the recorded groups, each in the form its count chose (short or
+// long rows; the LDS of the launch holds either layout); groups whose
+// records did not fit are left to k_radius_fill
 __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
-    __shared__ RecLds L;
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
     if (!records_valid(a)) return;                   // k_radius_fill searches every group
     const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
-    if (v == kRecOverflow || (v & kRecLongRows)) return;
+    if (v == kRecOverflow) return;
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;  // empty rows
-    radius_fill_rec_body(L, a, C, g - C.g0, min(v, static_cast<uint32_t>(kRecCap)));
-}
-
-// rows of the recorded groups in the long-row form
-__global__ __launch_bounds__(64) void k_radius_fill_rec_long(SearchArgs a) {
-    __shared__ RecLdsLong L;
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
-    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
-    if (!records_valid(a)) return;                   // k_radius_fill searches every group
-    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
-    if (v == kRecOverflow || !(v & kRecLongRows)) return;
-    const SearchCloud C = group_cloud(a, g);
-    if (!(C.r > 0.0f)) return;  // empty rows
-    radius_fill_rec_long_body(L, a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
+    if (v & kRecLongRows)
+        radius_fill_rec_long_body(*reinterpret_cast<RecLdsLong *>(g_radius_lds), a, C, g - C.g0,
+                                  min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
+    else
+        radius_fill_rec_body(*reinterpret_cast<RecLds *>(g_radius_lds), a, C, g - C.g0,
+                             min(v, static_cast<uint32_t>(kRecCap)));
 }
 
 template <int STAGE>
@@ -2330,10 +2321,8 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
             SFC_LAUNCH_CHECK("k_reset_spread");
         }
         if (record) {
-            k_radius_fill_rec<<<grid, 64, 0, s>>>(a);
+            k_radius_fill_rec<<<grid, 64, std::max(sizeof(RecLds), sizeof(RecLdsLong)), s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_fill_rec");
-            k_radius_fill_rec_long<<<grid, 64, 0, s>>>(a);
-            SFC_LAUNCH_CHECK("k_radius_fill_rec_long");
         }
         k_radius_fill<<<grid, 64, radius_lds_bytes(tab, true), s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");

@@ -40,19 +40,27 @@ KMAX = 32
 
 
 class Resident:
-    """Clouds and their octrees resident in device memory."""
+    """Clouds and their octrees resident in device memory.  A group of clouds
+    is built in memory sized by the node upper bound (so the build needs no
+    host round trip) and, with compact=True, then copied into exactly the
+    memory its actual trees need (octree_batch_compact); the budget is
+    charged the exact bytes, and the upper bound only has to fit while the
+    group is being built."""
 
-    def __init__(self, budget_bytes: int, curve="hilbert", bits: int = 21, leaf_size: int = 64):
+    def __init__(self, budget_bytes: int, curve="hilbert", bits: int = 21, leaf_size: int = 64,
+                 compact: bool = True):
         self.budget = int(budget_bytes)
         self.curve = curve
         self.bits = bits
         self.leaf = leaf_size
+        self.compact = compact
         self.groups = []       # (xyz, tree_mem, clouds table, first cloud id)
         self.cloud = []        # cloud id -> (group, index in group)
         self.used = 0
 
     def bytes_for(self, sizes) -> int:
-        """Device bytes a group of clouds would hold (points + trees)."""
+        """Device bytes a group of clouds needs while it is built (points +
+        trees at the node upper bound)."""
         L = B.load()
         nb = len(sizes)
         cl = (B.SfcCloud * nb)()
@@ -96,6 +104,17 @@ class Resident:
         B.check(L.build_linear_octree_batched(_ptr(xyz), nb, cl, _ptr(ws), ctypes.byref(wsb), stream), "build")
         torch.cuda.synchronize()
         del ws
+        if self.compact:
+            # the trees copied into exactly the memory their actual sizes need
+            cb = ctypes.c_size_t(0)
+            B.check(L.octree_batch_compact(nb, cl, None, ctypes.byref(cb), None, stream), "octree_batch_compact(size)")
+            cmem = torch.empty(max(cb.value, 256), dtype=torch.uint8, device="cuda")
+            out = (B.SfcCloud * nb)()
+            B.check(L.octree_batch_compact(nb, cl, _ptr(cmem), ctypes.byref(cb), out, stream), "octree_batch_compact")
+            torch.cuda.synchronize()
+            del mem
+            mem, cl = cmem, out
+            need = int(cb.value) + 12 * off
         g = len(self.groups)
         first = len(self.cloud)
         self.groups.append({"xyz": xyz, "mem": mem, "clouds": cl, "first": first, "sizes": sizes,

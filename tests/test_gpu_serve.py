@@ -107,13 +107,56 @@ def test_cloud_admission_by_memory():
     from paper_2603_06771_amd import serve
     a = datagen.lidar_tile(50000, seed=1)
     b = datagen.lidar_tile(80000, seed=2)
-    res = serve.Resident(budget_bytes=1 << 62)
+    res = serve.Resident(budget_bytes=1 << 62, compact=False)
     need_a = res.bytes_for([a.shape[0]])
     need_b = res.bytes_for([b.shape[0]])
-    res = serve.Resident(budget_bytes=need_a + need_b // 2)
+    res = serve.Resident(budget_bytes=need_a + need_b // 2, compact=False)
     announce("serve: admission")
     assert res.admit([a]) == [0]
     assert res.admit([b]) is None and res.used == need_a   # does not fit: nothing allocated
     res.drop(0)
     assert res.used == 0
     assert res.admit([b]) == [1]
+
+
+def test_compacted_trees_admit_more_with_same_results():
+    """Trees copied into exactly the memory their actual sizes need
+    (octree_batch_compact): the same budget holds more clouds, and searches
+    on the copies give the rows of the trees built in place."""
+    import torch
+    import paper_2603_06771_amd as sfc
+    from paper_2603_06771_amd import serve
+    clouds = [datagen.lidar_tile(60000, seed=90 + i) for i in range(6)]
+    need = serve.Resident(budget_bytes=1 << 62).bytes_for([60000])
+    budget = int(2.2 * need)
+    announce("serve: admission with and without compaction")
+    loose = serve.Resident(budget_bytes=budget, compact=False)
+    tight = serve.Resident(budget_bytes=budget, compact=True)
+    n_loose = sum(loose.admit([c]) is not None for c in clouds)
+    n_tight = sum(tight.admit([c]) is not None for c in clouds)
+    assert n_loose == 2 and n_tight > n_loose
+    assert tight.used < 0.5 * n_tight * need
+    for cid in range(n_loose):
+        t0, t1 = loose.octree(cid), tight.octree(cid)
+        for kernel, r in (("sphere", 1.5), ("square", 0.7)):
+            a = sfc.radius_search(t0, None, kernel, r, record=True)
+            b = sfc.radius_search(t1, None, kernel, r, record=True)
+            torch.cuda.synchronize()
+            for x, y in zip(a, b):
+                assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+        i0, d0 = sfc.knn_search(t0, None, 16)
+        i1, d1 = sfc.knn_search(t1, None, 16)
+        torch.cuda.synchronize()
+        assert np.array_equal(i0.cpu().numpy(), i1.cpu().numpy())
+        assert np.array_equal(d0.cpu().numpy().view(np.uint32), d1.cpu().numpy().view(np.uint32))
+    # an empty cloud and a one-point cloud compact too
+    announce("serve: compaction of an empty and a one-point cloud")
+    small = serve.Resident(budget_bytes=1 << 30, compact=True)
+    assert small.admit([np.zeros((0, 3), np.float32), a_point()]) == [0, 1]
+    c, o, i = sfc.radius_search(small.octree(1), None, "sphere", 1.0)
+    torch.cuda.synchronize()
+    assert int(o[-1]) == 1
+
+
+def a_point():
+    return np.array([[1.0, 2.0, 3.0]], np.float32)
