@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--record-batched", action="store_true",
                     help="batched: fill every cloud from recorded hits instead of the autotuner's per-group choice")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
+                    help="run a plain 256 MiB device copy and a 256 MiB elementwise kernel first (reference "
+                         "dispatches for HBM counters)")
     ap.add_argument("--workload", default="radius", choices=["radius", "batched", "served", "subset"],
                     help="radius: 10M LiDAR radius sweep (default); batched: 256 clouds, build + radius search; "
                          "served: 64 resident clouds, Poisson radius / k-NN requests")
@@ -549,9 +550,13 @@ def main():
     xyz = torch.from_numpy(pts).cuda()
     n = pts.shape[0]
     if args.copy_calib:
+        # reference dispatches of known size for the HBM counters: the
+        # runtime's device copy and an elementwise kernel (256 MiB read,
+        # 256 MiB written each)
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()

@@ -9,10 +9,14 @@
         <write_counter_collection.csv> [kernel-substring]
     python -m paper_2603_06771_amd.rocprof_summary record <fetch.csv> <write.csv> <kernel> <source>
     python -m paper_2603_06771_amd.rocprof_summary stage <fetch.csv> <write.csv> <k1,k2,...> <stages> <source>
+    python -m paper_2603_06771_amd.rocprof_summary call <fetch.csv> <write.csv> <k1[@grid],k2,...> <source>
 
 `traffic` reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the matching
-kernel, scaled by what the same counters read for the plain device copy of
-known size in the same run (the largest elementwise copy dispatch).
+kernel, scaled by what the same counters read for a reference dispatch of
+known size in the same run (256 MiB read, 256 MiB written): by default the
+runtime's device copy (`copyBuffer`); a trailing argument `calib=<name>`
+picks another reference, e.g. `calib=elementwise` for the elementwise kernel
+that bench.py --copy-calib also runs.
 """
 from __future__ import annotations
 
@@ -21,6 +25,14 @@ import statistics
 import sys
 
 COPY_BYTES = 2 * (64 << 20) * 4  # 256 MiB read + 256 MiB written by the calibration copy
+CALIB = "copyBuffer"  # name (substring) of the reference dispatch
+
+
+def _ref(rows, calib):
+    """Counter value of the reference dispatch: the largest one whose kernel
+    name contains `calib`."""
+    vals = [v for _, k, v in rows if calib in k]
+    return max(vals) if vals else None
 
 
 def stats(path: str, top: int = 25) -> str:
@@ -126,21 +138,18 @@ def _per_dispatch(path: str, counter: str):
     return rows
 
 
-def traffic(fetch_path: str, write_path: str, kernel: str = "k_radius_fill", min_kib: float = 1024.0) -> str:
+def traffic(fetch_path: str, write_path: str, kernel: str = "k_radius_fill", min_kib: float = 1024.0,
+            calib: str = CALIB) -> str:
     """Per-dispatch FETCH_SIZE / WRITE_SIZE of `kernel` (dispatches reading or
     writing at least min_kib), scaled by the calibration copy's readings."""
     fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
     write = _per_dispatch(write_path, "WRITE_SIZE")
 
-    def copy_ref(rows):
-        vals = [v for _, k, v in rows if "copyBuffer" in k]
-        return max(vals) if vals else None
-
-    fc, wc = copy_ref(fetch), copy_ref(write)
+    fc, wc = _ref(fetch, calib), _ref(write, calib)
     half = COPY_BYTES // 2
     ffac = half / (fc * 1024) if fc else 1.0
     wfac = half / (wc * 1024) if wc else 1.0
-    lines = [f"calibration: plain device copy of {half} B (__amd_rocclr_copyBuffer)",
+    lines = [f"calibration: reference dispatch '{calib}' reading and writing {half} B each",
              f"  FETCH_SIZE {fc} KiB -> scale {ffac:.4f};  WRITE_SIZE {wc} KiB -> scale {wfac:.4f}",
              f"{'dispatch':>8s} {'fetch_KiB':>12s} {'write_KiB':>12s} {'fetch_B_scaled':>15s} {'write_B_scaled':>15s}  kernel"]
     wmap = {d: v for d, k, v in write if kernel in k}
@@ -166,13 +175,14 @@ def source_sha(path: str) -> str:
     return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
 
 
-def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, min_kib: float = 1024.0) -> dict:
+def traffic_record(fetch_path: str, write_path: str, kernel: str, source: str, min_kib: float = 1024.0,
+                   calib: str = CALIB) -> dict:
     """Mean scaled HBM bytes per launch of `kernel`, tagged with the hash of
     the kernel's source file (a reader uses it only while the hash matches)."""
     fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
     write = {d: v for d, k, v in _per_dispatch(write_path, "WRITE_SIZE") if kernel in k}
-    fc = max(v for _, k, v in fetch if "copyBuffer" in k)
-    wc = max(v for _, k, v in _per_dispatch(write_path, "WRITE_SIZE") if "copyBuffer" in k)
+    fc = _ref(fetch, calib)
+    wc = _ref(_per_dispatch(write_path, "WRITE_SIZE"), calib)
     half = COPY_BYTES // 2
     ffac, wfac = half / (fc * 1024), half / (wc * 1024)
     f_b, w_b = [], []
@@ -190,14 +200,14 @@ def _base(kernel_name: str) -> str:
     return kernel_name.split("(")[0].split("::")[-1]
 
 
-def stage_record(fetch_path: str, write_path: str, kernels: list, stages: int, source: str) -> dict:
+def stage_record(fetch_path: str, write_path: str, kernels: list, stages: int, source: str,
+                 calib: str = CALIB) -> dict:
     """Scaled HBM bytes of a stage made of several kernels (exact base names):
     the sum over every dispatch of those kernels in the run, divided by the
     number of stages the run executed; tagged like traffic_record."""
     fetch = _per_dispatch(fetch_path, "FETCH_SIZE")
     write = _per_dispatch(write_path, "WRITE_SIZE")
-    fc = max(v for _, k, v in fetch if "copyBuffer" in k)
-    wc = max(v for _, k, v in write if "copyBuffer" in k)
+    fc, wc = _ref(fetch, calib), _ref(write, calib)
     half = COPY_BYTES // 2
     ffac, wfac = half / (fc * 1024), half / (wc * 1024)
     names = set(kernels)
@@ -211,11 +221,64 @@ def stage_record(fetch_path: str, write_path: str, kernels: list, stages: int, s
             per[_base(k)][1] += v * 1024 * ffac
     return {"kernels": sorted(names), "source_sha": source_sha(source), "stages": stages,
             "fetch_bytes_per_launch": f_sum / stages, "write_bytes_per_launch": w_sum / stages,
-            "bytes_per_launch": (f_sum + w_sum) / stages, "fetch_scale": ffac, "write_scale": wfac,
+            "bytes_per_launch": (f_sum + w_sum) / stages, "fetch_scale": ffac, "write_scale": wfac, "calib": calib,
             "fetch_bytes_by_kernel": {k: {"dispatches": c, "bytes_per_stage": b / stages} for k, (c, b) in per.items()}}
 
 
+def _rows_grid(path: str, counter: str):
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return rows
+
+
+def call_record(fetch_path: str, write_path: str, kernels: list, source: str, calib: str = CALIB,
+                wcalib: str | None = None) -> dict:
+    """Scaled HBM bytes of one call made of several kernels, each launched
+    once per call: the sum over `kernels` of the mean scaled bytes per
+    dispatch of that kernel.  An entry is a base kernel name, optionally
+    with `@<grid size>` to keep only the dispatches of that grid (kernels
+    that other steps of the run also launch, at other sizes).  Tagged like
+    traffic_record.  wcalib: the reference for WRITE_SIZE when it differs
+    from the one for FETCH_SIZE ("raw": no scaling)."""
+    fetch = _rows_grid(fetch_path, "FETCH_SIZE")
+    write = _rows_grid(write_path, "WRITE_SIZE")
+    wcalib = wcalib or calib
+    fc = _ref([(d, k, v) for d, k, _, v in fetch], calib)
+    half = COPY_BYTES // 2
+    ffac = half / (fc * 1024)
+    if wcalib == "raw":
+        wfac = 1.0
+    else:
+        wfac = half / (_ref([(d, k, v) for d, k, _, v in write], wcalib) * 1024)
+    per = {}
+    f_sum = w_sum = 0.0
+    for spec in kernels:
+        name, _, grid = spec.partition("@")
+
+        def sel(rows):
+            return [v for _, k, g, v in rows if _base(k) == name and (not grid or g == int(grid))]
+        fv, wv = sel(fetch), sel(write)
+        if not fv or not wv:
+            raise ValueError(f"no dispatch of {spec}")
+        fb, wb = statistics.mean(fv) * 1024 * ffac, statistics.mean(wv) * 1024 * wfac
+        per[spec] = {"dispatches": len(fv), "fetch_bytes": fb, "write_bytes": wb}
+        f_sum += fb
+        w_sum += wb
+    return {"kernels": list(kernels), "source_sha": source_sha(source), "fetch_bytes_per_launch": f_sum,
+            "write_bytes_per_launch": w_sum, "bytes_per_launch": f_sum + w_sum, "fetch_scale": ffac,
+            "write_scale": wfac, "calib": calib, "wcalib": wcalib, "by_kernel": per}
+
+
 if __name__ == "__main__":
+    WCALIB = None
+    while sys.argv[-1].startswith(("calib=", "wcalib=")):
+        opt = sys.argv.pop()
+        if opt.startswith("wcalib="):
+            WCALIB = opt[len("wcalib="):]
+        else:
+            CALIB = opt[len("calib="):]
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "l2":
@@ -229,9 +292,13 @@ if __name__ == "__main__":
     elif sys.argv[1] == "stage":
         import json
         print(json.dumps(stage_record(sys.argv[2], sys.argv[3], sys.argv[4].split(","), int(sys.argv[5]),
-                                      sys.argv[6]), indent=1))
+                                      sys.argv[6], calib=CALIB), indent=1))
+    elif sys.argv[1] == "call":
+        import json
+        print(json.dumps(call_record(sys.argv[2], sys.argv[3], sys.argv[4].split(","), sys.argv[5], calib=CALIB,
+                                     wcalib=WCALIB), indent=1))
     elif sys.argv[1] == "record":
         import json
-        print(json.dumps(traffic_record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5]), indent=1))
+        print(json.dumps(traffic_record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], calib=CALIB), indent=1))
     else:
-        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "k_radius_fill"))
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "k_radius_fill", calib=CALIB))
