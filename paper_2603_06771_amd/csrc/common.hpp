@@ -56,7 +56,9 @@ inline int grid_for(int64_t n, int block, int cap = 1 << 20) {
 // -------------------------------------------------------------- device side
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// the lane mask of p (the builtin on the i1 value: no round trip through a
+// vector register)
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Orders the LDS accesses of a workgroup made of a single wave: LDS writes of
 // any lane before the call are seen by LDS reads of every lane after it.  A

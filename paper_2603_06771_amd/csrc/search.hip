@@ -117,6 +117,28 @@ __device__ __forceinline__ bool point_hit(const float4 &p, float qx, float qy, f
     }
 }
 
+// point_hit as a lane mask, taken straight from the comparisons (ordered
+// less-than, as `<` is), so a caller that needs the mask of the wave's hits
+// gets it without turning every lane's result into a 0/1 value first.  Every
+// lane of the wave must be active.
+template <int KERNEL>
+__device__ __forceinline__ uint64_t hit_mask(const float4 &p, float qx, float qy, float qz, float r, float r2) {
+    constexpr int kOlt = 4;  // the ordered less-than predicate of the compare intrinsic
+    const float dx = fsub(p.x, qx), dy = fsub(p.y, qy);
+    if constexpr (KERNEL == SFC_SPHERE) {
+        const float dz = fsub(p.z, qz);
+        return __builtin_amdgcn_fcmpf(fadd(fadd(fmul(dx, dx), fmul(dy, dy)), fmul(dz, dz)), r2, kOlt);
+    } else if constexpr (KERNEL == SFC_CIRCLE) {
+        return __builtin_amdgcn_fcmpf(fadd(fmul(dx, dx), fmul(dy, dy)), r2, kOlt);
+    } else if constexpr (KERNEL == SFC_CUBE) {
+        const float dz = fsub(p.z, qz);
+        return __builtin_amdgcn_fcmpf(fabsf(dx), r, kOlt) & __builtin_amdgcn_fcmpf(fabsf(dy), r, kOlt) &
+               __builtin_amdgcn_fcmpf(fabsf(dz), r, kOlt);
+    } else {
+        return __builtin_amdgcn_fcmpf(fabsf(dx), r, kOlt) & __builtin_amdgcn_fcmpf(fabsf(dy), r, kOlt);
+    }
+}
+
 __device__ __forceinline__ float dist2(const float4 &p, float qx, float qy, float qz) {
     const float dx = fsub(p.x, qx), dy = fsub(p.y, qy), dz = fsub(p.z, qz);
     return fadd(fadd(fmul(dx, dx), fmul(dy, dy)), fmul(dz, dz));
@@ -834,9 +856,10 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
                 uint32_t mlo = 0, mhi = 0;
                 uint32_t t = t0;
                 auto test = [&](uint32_t u) {
-                    const bool h = point_hit<KERNEL>(L.pts[u], qx, qy, qz, r, r2);
-                    cnt += h ? 1u : 0u;
-                    const uint64_t m = ballot(h);
+                    // the hit mask straight from the comparison; the lane's own
+                    // bit of it counts (no 0/1 value in a vector register)
+                    const uint64_t m = hit_mask<KERNEL>(L.pts[u], qx, qy, qz, r, r2);
+                    cnt += __builtin_amdgcn_inverse_ballot_w64(m) ? 1u : 0u;
                     const int at = static_cast<int>(u - t0);
                     mlo = writelane_u32(static_cast<uint32_t>(m), at, mlo);
                     mhi = writelane_u32(static_cast<uint32_t>(m >> 32), at, mhi);
