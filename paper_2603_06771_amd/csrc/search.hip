@@ -1739,9 +1739,15 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
         }
     }
 
+    // Entries past k hold 0, the smallest key, so they never move up.  Keys
+    // are non-negative and below the bit pattern of +inf as a double (d2 <=
+    // +inf as a float keeps the top 12 bits at most 0x7F8), so as IEEE doubles
+    // they order exactly as the integers do and the insertion compares them
+    // with one 64-bit float min or max each (denormal doubles, the keys with
+    // d2 = 0, are preserved in this build).
     int64_t best[KMAX];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) best[i] = i < k ? kPad : int64_t(-1);
+    for (int i = 0; i < KMAX; ++i) best[i] = i < k ? kPad : int64_t(0);
 
     bool active = q.valid;
     float lo2 = -1.0f;  // points with d2 <= lo2 were handled by an earlier round
@@ -1808,10 +1814,14 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
                         const float d = dist2(p, q.x, q.y, q.z);
                         const int64_t x = pack(d, __float_as_uint(p.w));
                         if (((lm >> o) & 1ull) && d > lo2 && d <= bound && x < best[0]) {
+                            // the list (descending) without its largest key, x
+                            // inserted: entry i becomes max(best[i + 1], min(best[i], x))
+                            const double xd = __longlong_as_double(x);
 #pragma unroll
                             for (int i = 0; i < KMAX; ++i) {
-                                const int64_t nxt = (i + 1 < KMAX) ? best[i + 1] : int64_t(-1);
-                                best[i] = nxt > x ? nxt : (best[i] > x ? x : best[i]);
+                                const double lo = fmin(__longlong_as_double(best[i]), xd);
+                                best[i] = i + 1 < KMAX ? __double_as_longlong(fmax(__longlong_as_double(best[i + 1]), lo))
+                                                       : __double_as_longlong(lo);
                             }
                         }
                     }
