@@ -1632,6 +1632,18 @@ __global__ void k_zero_rows(uint32_t *counts, uint64_t *offsets, int64_t nq) {
 // ------------------------------------------------------------------ k-NN
 namespace {
 
+// Minimum and maximum of two k-NN keys viewed as doubles.  Keys are never
+// NaNs, so no operand needs quietening first.
+__device__ __forceinline__ double key_min(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double key_max(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 constexpr int64_t kPad = static_cast<int64_t>((0x7F800000ull << 32) | 0xFFFFFFFFull);  // (+inf, no index)
 
 __device__ __forceinline__ int64_t pack(float d, uint32_t i) {
@@ -1745,9 +1757,12 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
     // they order exactly as the integers do and the insertion compares them
     // with one 64-bit float min or max each (denormal doubles, the keys with
     // d2 = 0, are preserved in this build).
-    int64_t best[KMAX];
+    // No key is a NaN, so the min and max are issued directly: the compiler's
+    // fmin/fmax would first quieten every operand with one more 64-bit op.
+    double best[KMAX];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) best[i] = i < k ? kPad : int64_t(0);
+    for (int i = 0; i < KMAX; ++i) best[i] = __longlong_as_double(i < k ? kPad : int64_t(0));
+    auto kth_of = [&]() { return __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(best[0])) >> 32)); };
 
     bool active = q.valid;
     float lo2 = -1.0f;  // points with d2 <= lo2 were handled by an earlier round
@@ -1777,7 +1792,7 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
             for (int c0 = 0; c0 < ncand; c0 += kWave) {
                 const int m = min(kWave, ncand - c0);
                 float thr = bound;
-                const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
+                const float kth = kth_of();
                 if (kth < thr) thr = kth;
                 uint64_t lm = 0;
                 if (active) {
@@ -1813,15 +1828,14 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
                         const uint32_t o = L.owner[t];
                         const float d = dist2(p, q.x, q.y, q.z);
                         const int64_t x = pack(d, __float_as_uint(p.w));
-                        if (((lm >> o) & 1ull) && d > lo2 && d <= bound && x < best[0]) {
+                        const double xd = __longlong_as_double(x);
+                        if (((lm >> o) & 1ull) && d > lo2 && d <= bound && xd < best[0]) {
                             // the list (descending) without its largest key, x
                             // inserted: entry i becomes max(best[i + 1], min(best[i], x))
-                            const double xd = __longlong_as_double(x);
 #pragma unroll
                             for (int i = 0; i < KMAX; ++i) {
-                                const double lo = fmin(__longlong_as_double(best[i]), xd);
-                                best[i] = i + 1 < KMAX ? __double_as_longlong(fmax(__longlong_as_double(best[i + 1]), lo))
-                                                       : __double_as_longlong(lo);
+                                const double lo = key_min(best[i], xd);
+                                best[i] = i + 1 < KMAX ? key_max(best[i + 1], lo) : lo;
                             }
                         }
                     }
@@ -1839,7 +1853,7 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
         }
         traverse(L, C.nodes, C.child, accept, sweep, start);
         // done: the answer lies within the radius already searched
-        const float kth = __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(best[0]) >> 32));
+        const float kth = kth_of();
         if (round == 0) active = active && !(tau <= R1 || kth <= R1);
         else active = false;
         lo2 = R1;
@@ -1850,7 +1864,7 @@ __global__ __launch_bounds__(64) void k_knn(SearchArgs a) {
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) {
             if (i < k) {
-                const uint64_t v = static_cast<uint64_t>(best[i]);
+                const uint64_t v = static_cast<uint64_t>(__double_as_longlong(best[i]));
                 oi[k - 1 - i] = static_cast<uint32_t>(v);
                 od[k - 1 - i] = __uint_as_float(static_cast<uint32_t>(v >> 32));
             }
