@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # the fill stage of a recorded-hits search: the two record-writing forms and
 # the search fill for groups whose records did not fit
-FILL_STAGE = "k_radius_fill_rec + k_radius_fill"
+FILL_STAGE = "k_radius_fill_rec + k_radius_fill_rows + k_radius_fill"
 # one radius_search call: count pass, scan of the counts, fill stage
 SEARCH = "radius_search: k_radius_count_rec + k_scan_* + " + FILL_STAGE
 SEARCH_NO_RECORD = "radius_search: k_radius_count + k_scan_* + k_radius_fill"

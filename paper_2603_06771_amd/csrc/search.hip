@@ -68,9 +68,6 @@ namespace {
 #ifndef SFC_ROWCAP
 #define SFC_ROWCAP 32
 #endif
-#ifndef SFC_REC_CHUNKL
-#define SFC_REC_CHUNKL 8
-#endif
 #ifndef SFC_REC_BATCH
 #define SFC_REC_BATCH 4
 #endif
@@ -80,11 +77,11 @@ namespace {
 #ifndef SFC_REC_CAP
 #define SFC_REC_CAP 4096
 #endif
-#ifndef SFC_REC_LINE
-#define SFC_REC_LINE 32
-#endif
 #ifndef SFC_CHUNK
 #define SFC_CHUNK 16
+#endif
+#ifndef SFC_REC_ROWBLK
+#define SFC_REC_ROWBLK 16
 #endif
 constexpr int kStack = SFC_STACK;     // traversal stack entries
 constexpr int kCand = SFC_CAND;       // candidate nodes held before a sweep
@@ -803,10 +800,10 @@ __device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, con
 // With REC (SFC_RECORD_HITS) the wave also records, per staged point that
 // is a neighbour of at least one of its queries, the point's original index
 // and the mask of those queries, in staging order, into the group's region
-// of the workspace: k_radius_fill_rec then writes the rows from the records
-// alone.  Every touched node is staged and tested (a contained node is not
-// counted from its size), so the records hold every neighbour in the order
-// k_radius_fill would write them.  A group whose records do not fit kRecCap,
+// of the workspace: k_radius_fill_rec and k_radius_fill_rows then write the
+// rows from the records alone.  Every touched node is staged and tested (a
+// contained node is not counted from its size), so the records hold every
+// neighbour in the order k_radius_fill would write them.  A group whose records do not fit kRecCap,
 // or that is deferred, is marked kRecOverflow and left to k_radius_fill.
 template <int KERNEL, bool REC, int STAGE>
 __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const SearchArgs &a, const SearchCloud &C,
@@ -924,24 +921,18 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
     }
 }
 
-// Writing the rows of a group from its records (SFC_RECORD_HITS): per
-// record, every lane whose bit is set appends the record to its LDS row.
-// No traversal and no distance test.  Two forms, chosen per group by the
-// count pass from the group's mean row length:
-//  - short rows: rows hold one-byte slots into the current batch of up to
-//    256 records and are written out (two rows per step, one per half wave)
+// Writing the rows of a group from its records (SFC_RECORD_HITS): no
+// traversal and no distance test.  Two forms, chosen per group by the count
+// pass from the group's mean row length, each a kernel of its own (so each
+// keeps its own register and LDS footprint):
+//  - short rows (k_radius_fill_rec): per record, every lane whose bit is set
+//    appends a one-byte slot into the current batch of up to 256 records to
+//    its LDS row; rows are written out (two rows per step, one per half wave)
 //    once they could overflow and after every batch;
-//  - long rows: rows outlive chunks and batches (slots into a ring of the
-//    last 256 records); a row is written out up to the next 128-byte boundary
-//    of its output once it reaches it, so every store but a row's first and
-//    last (and rare forced ones) is one whole aligned line.
-constexpr int kRecLine = SFC_REC_LINE;           // long rows: entries written per aligned run
-constexpr int kRecChunkL = SFC_REC_CHUNKL;       // long rows: records between flush checks
-constexpr int kRecRowL = kRecLine + kRecChunkL;  // long rows: entries a row can reach
+//  - long rows (k_radius_fill_rows): the rows are written one query after
+//    another straight from the records held in registers (below).
 constexpr int kRecBatch = SFC_REC_BATCH;         // short rows: chunks of 64 records per load round trip and slot table
-static_assert(kRecChunkL <= 16 && kRecBatch >= 1 && kRecBatch <= 4 && kRecLine <= 64 &&
-                  (kRecLine & (kRecLine - 1)) == 0 && kRecChunkL < kRecLine,
-              "record fill shapes");
+static_assert(kRecBatch >= 1 && kRecBatch <= 4, "record fill shapes");
 
 // Rows being written out are listed compactly: entry i holds the row's
 // output position and its lane and counts packed in one word, so a writing
@@ -1042,132 +1033,116 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
     }
 }
 
-// Long rows hold one-byte slots into a ring of the last 256 records (two
-// batches of 128): before a batch overwrites its half of the ring, rows whose
-// oldest entry lies there are written out whole (rows are first-in
-// first-out, so the oldest entry decides).
-constexpr int kRingHalf = 2 * kWave;  // records per long-row batch
-static_assert(2 * kRingHalf == 256, "ring slots are one byte");
+// Long rows, written one query after another: the wave holds up to kRowBlk
+// chunks of 64 records in registers (lane = record; 16 chunks cover the
+// records of nearly every long-row group, so the wave loads nothing after its
+// first store: on this GPU a wait for a load also waits for every store
+// issued before it).  For each query the lanes whose record mask holds its
+// bit store their original index at the row's next positions (each lane's
+// rank among them from mbcnt, which also adds the entries already written).
+// A group's rows are consecutive in the output, so its stores run through
+// one region in order; a record chunk costs a query five vector
+// instructions and one store, whatever its hits.
+constexpr int kRowBlk = SFC_REC_ROWBLK;
+static_assert(kRowBlk >= 1 && kRowBlk <= 16, "record chunks held per pass");
 
-struct RecLdsLong {
-    uint8_t rows[kWave * (kRecRowL + 1)];  // slots into ring; odd stride spreads the append cursors
-    uint32_t ring[2 * kRingHalf];          // original indices: record position mod 256
-    uint64_t fpos[kWave];   // by list entry: output position
-    uint32_t fmeta[kWave];  // by list entry: lane | written << 8 | taken off << 16 | left << 24
-};
+// The queries of `qm` against NCH chunks of records: word[u] / pi[u] hold
+// chunk u's mask words (the low ones for queries 0-31, the high ones for
+// 32-63) and original indices.  start / len / done: per lane, its row's first
+// output position, length and entries written so far.
+template <int NCH>
+__device__ __forceinline__ void rows_queries(uint64_t qm, const uint32_t (&word)[kRowBlk],
+                                             const uint32_t (&pi)[kRowBlk], uint64_t start, uint32_t len,
+                                             uint32_t &done, uint32_t *__restrict__ out) {
+    for (; qm; qm &= qm - 1) {
+        const int j = __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(qm)) - 1);
+        const uint32_t rl = readlane_u32(len, j);
+        const uint32_t w = readlane_u32(done, j);
+        const uint32_t bit = 1u << (j & 31);
+        uint64_t m[NCH];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            m[u] = ballot((word[u] & bit) != 0u);
+            tot += static_cast<uint32_t>(__popcll(m[u]));
+        }
+        uint32_t *const row = out + readlane_u64(start, j);
+        if (w + tot <= rl) {  // always, when the offsets come from this count
+            // every chunk's byte offsets in a register of its own, all computed
+            // before the first store (none sunk into the predicated store
+            // blocks, where one register would serve them all and each
+            // offset would wait for the previous store to release it)
+            uint32_t off[NCH];
+            uint32_t at = w;
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                off[u] = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), at)) * 4u;
+                at += static_cast<uint32_t>(__popcll(m[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) asm volatile("" : "+v"(off[u]));
+#pragma unroll
+            for (int u = 0; u < NCH; ++u)
+                if (__builtin_amdgcn_inverse_ballot_w64(m[u]))
+                    *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(row) + off[u]) = pi[u];
+        } else {  // a shorter row (offsets not from this count) takes the first of its entries
+            uint32_t at = w;
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                const uint32_t pos = at + rank_below(m[u]);
+                if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && pos < rl) row[pos] = pi[u];
+                at += static_cast<uint32_t>(__popcll(m[u]));
+            }
+        }
+        done = writelane_u32(w + tot, j, done);
+    }
+}
 
-__device__ __forceinline__ void radius_fill_rec_long_body(RecLdsLong &L, const SearchArgs &a, const SearchCloud &C,
-                                                          int64_t lg, uint32_t n) {
-    constexpr int kStride = kRecRowL + 1;
+// the chunk count as a template argument (no per-chunk checks in the loops)
+template <int NCH = kRowBlk>
+__device__ __forceinline__ void rows_block(int nch, uint64_t rows, const uint32_t (&lo)[kRowBlk],
+                                           const uint32_t (&hi)[kRowBlk], const uint32_t (&pi)[kRowBlk],
+                                           uint64_t start, uint32_t len, uint32_t &done, uint32_t *out) {
+    if constexpr (NCH > 1) {
+        if (nch < NCH) {
+            rows_block<NCH - 1>(nch, rows, lo, hi, pi, start, len, done, out);
+            return;
+        }
+    }
+    rows_queries<NCH>(rows & 0xFFFFFFFFull, lo, pi, start, len, done, out);
+    rows_queries<NCH>(rows & ~0xFFFFFFFFull, hi, pi, start, len, done, out);
+}
+
+__device__ __forceinline__ void radius_fill_rows_body(const SearchArgs &a, const SearchCloud &C, int64_t lg,
+                                                      uint32_t n) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
-    const int64_t gg = lg + C.g0;
     int64_t row;
     const Query q = lane_query(a, C, lr, &row);
     const int64_t orow = q.valid ? row : 0;
     const uint64_t o0 = a.offsets[orow], o1 = a.offsets[orow + 1];
-    uint64_t gpos = q.valid ? o0 : 0ull;
-    const uint64_t gend = q.valid ? o1 : 0ull;
-    uint64_t left = gend > gpos ? gend - gpos : 0ull;
-    uint32_t nb = 0;
-    uint8_t *myrow = L.rows + lane * kStride;
-    uint32_t *out = a.indices;
-    // kWave / kRecLine rows per step, lane e of a row's part writes its entry e
-    constexpr int kPerStep = kWave / kRecLine;
-    const int sub = lane / kRecLine, e = lane % kRecLine;
-    // Takes `drop` (at most kRecLine, per lane) entries off the front of each
-    // row and writes them out; the kept entries move to the row's start in the
-    // same step (each lane reads its entry before any lane writes).
-    auto flush = [&](uint32_t drop) {
-        const bool go = drop > 0;
-        const uint64_t fm = ballot(go);
-        if (!fm) return;
-        const int nf = __popcll(fm);
-        if (go) {
-            const uint32_t i = rank_below(fm);
-            L.fpos[i] = gpos;
-            L.fmeta[i] = static_cast<uint32_t>(lane) | (static_cast<uint32_t>(left < drop ? left : drop) << 8) |
-                         (drop << 16) | ((nb - drop) << 24);
-        }
-        wave_sync();
-        for (int i0 = 0; i0 < nf; i0 += kPerStep) {
-            const int i = i0 + sub;
-            if (i < nf) {
-                const uint32_t meta = L.fmeta[i];
-                const uint64_t pos = L.fpos[i];
-                uint8_t *rw = L.rows + (meta & 0xFFu) * kStride;
-                const uint32_t cnt = (meta >> 8) & 0xFFu, drop_l = (meta >> 16) & 0xFFu, rem = meta >> 24;
-                // both reads stay inside the row (e < kRecLine < kStride; drop + e clamped)
-                const uint32_t slot = rw[e];
-                const uint8_t keep = rw[min(drop_l + static_cast<uint32_t>(e), static_cast<uint32_t>(kStride - 1))];
-                if (static_cast<uint32_t>(e) < cnt) out[pos + e] = L.ring[slot];
-                if (static_cast<uint32_t>(e) < rem) rw[e] = keep;
-            }
-        }
-        if (go) {
-            gpos += drop;
-            left -= left < drop ? left : drop;
-            nb -= drop;
-        }
-        wave_sync();
-    };
-    // entries up to the row's next line boundary, once it holds them
-    auto to_boundary = [&]() {
-        const uint32_t to_line = kRecLine - static_cast<uint32_t>(gpos & (kRecLine - 1));
-        return nb >= to_line ? to_line : 0u;
-    };
+    const uint64_t start = q.valid ? o0 : 0ull;
+    // counts are 32-bit, so a row's length is too
+    const uint32_t len = q.valid && o1 > o0 ? static_cast<uint32_t>(o1 - o0) : 0u;
+    uint32_t done = 0;  // entries of the lane's row written so far
+    const uint64_t rows = ballot(len > 0);
     const uint32_t *ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
     const uint64_t *rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
-    uint32_t k = 0;  // batch number
-    for (uint32_t b0 = 0; b0 < n; b0 += kRingHalf, ++k) {
-        constexpr int kPer = kRingHalf / kWave;
-        uint32_t bpi[kPer], blo[kPer], bhi[kPer];
+    for (uint32_t b0 = 0; b0 < n; b0 += kRowBlk * kWave) {
+        uint32_t pi[kRowBlk], lo[kRowBlk], hi[kRowBlk];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const uint32_t r = b0 + u * kWave + lane;
-            const bool have = r < n;
-            const uint64_t pm = have ? rmask[r] : 0ull;
-            bpi[u] = have ? ridx[r] : 0u;
-            blo[u] = static_cast<uint32_t>(pm);
-            bhi[u] = static_cast<uint32_t>(pm >> 32);
+        for (int u = 0; u < kRowBlk; ++u) {
+            const uint32_t k = b0 + u * kWave + lane;
+            const bool have = k < n;
+            const uint64_t pm = have ? rmask[k] : 0ull;
+            pi[u] = have ? ridx[k] : 0u;
+            lo[u] = static_cast<uint32_t>(pm);
+            hi[u] = static_cast<uint32_t>(pm >> 32);
         }
-        const uint32_t h = k & 1u;  // ring half this batch takes
-        if (k >= 2) {
-            flush(to_boundary());  // afterwards every row holds fewer than kRecLine entries
-            // the half still holds batch k - 2: rows starting there are written out whole
-            flush(nb > 0 && (static_cast<uint32_t>(myrow[0]) >> 7) == h ? nb : 0u);
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) L.ring[h * kRingHalf + u * kWave + lane] = bpi[u];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const uint32_t c0 = b0 + u * kWave;
-            if (c0 >= n) break;
-            const uint32_t m = min(n - c0, static_cast<uint32_t>(kWave));
-            const uint32_t lo = blo[u], hi = bhi[u];
-            const uint32_t base = h * kRingHalf + u * kWave;
-            for (uint32_t j0 = 0; j0 < m; j0 += kRecChunkL) {
-                flush(to_boundary());  // afterwards nb < kRecLine, so the chunk fits
-                const uint32_t je = min(m, j0 + kRecChunkL);
-                uint8_t *w = myrow + nb;
-                auto append = [&](uint32_t j) {
-                    const uint64_t mk = (static_cast<uint64_t>(readlane_u32(hi, static_cast<int>(j))) << 32) |
-                                        readlane_u32(lo, static_cast<int>(j));
-                    *w = static_cast<uint8_t>(base + j);
-                    w += static_cast<uint32_t>(mk >> lane) & 1u;
-                };
-                if (je - j0 == static_cast<uint32_t>(kRecChunkL)) {
-#pragma unroll
-                    for (int v = 0; v < kRecChunkL; ++v) append(j0 + v);
-                } else {
-                    for (uint32_t j = j0; j < je; ++j) append(j);
-                }
-                nb = static_cast<uint32_t>(w - myrow);
-            }
-        }
+        const int nch = static_cast<int>(min((n - b0 + kWave - 1) / kWave, static_cast<uint32_t>(kRowBlk)));
+        rows_block(nch, rows, lo, hi, pi, start, len, done, a.indices);
     }
-    flush(to_boundary());  // a row may hold up to kRecRowL entries; afterwards fewer than kRecLine,
-    flush(nb);             // which one step writes
 }
 
 // One query's row [pos, end): contained candidates are copied from the
@@ -1525,24 +1500,35 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
     }
 }
 
-// rows of the recorded groups, each in the form its count chose (short or
-// long rows; the LDS of the launch holds either layout); groups whose
-// records did not fit are left to k_radius_fill
+// Rows of the recorded groups that took the short-row form; the long-row
+// groups are k_radius_fill_rows' and those whose records did not fit
+// k_radius_fill's.  One wave per group, as in the count: a wave that took
+// several groups in turn would wait, before each next group's loads, for
+// every store of the previous one.
 __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
+    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    if (v == kRecOverflow || (v & kRecLongRows)) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
     if (!records_valid(a)) return;                   // k_radius_fill searches every group
-    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
-    if (v == kRecOverflow) return;
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;  // empty rows
-    if (v & kRecLongRows)
-        radius_fill_rec_long_body(*reinterpret_cast<RecLdsLong *>(g_radius_lds), a, C, g - C.g0,
-                                  min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
-    else
-        radius_fill_rec_body(*reinterpret_cast<RecLds *>(g_radius_lds), a, C, g - C.g0,
-                             min(v, static_cast<uint32_t>(kRecCap)));
+    radius_fill_rec_body(*reinterpret_cast<RecLds *>(g_radius_lds), a, C, g - C.g0,
+                         min(v, static_cast<uint32_t>(kRecCap)));
+}
+
+// Rows of the recorded groups that took the long-row form.
+__global__ __launch_bounds__(64) void k_radius_fill_rows(SearchArgs a) {
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    if (v == kRecOverflow || !(v & kRecLongRows)) return;
+    if (a.offsets[a.nq_total] > a.capacity) return;
+    if (!records_valid(a)) return;
+    const SearchCloud C = group_cloud(a, g);
+    if (!(C.r > 0.0f)) return;
+    radius_fill_rows_body(a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
 }
 
 template <int STAGE>
@@ -2368,8 +2354,10 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
             SFC_LAUNCH_CHECK("k_reset_spread");
         }
         if (record) {
-            k_radius_fill_rec<<<grid, 64, std::max(sizeof(RecLds), sizeof(RecLdsLong)), s>>>(a);
+            k_radius_fill_rec<<<grid, 64, sizeof(RecLds), s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_fill_rec");
+            k_radius_fill_rows<<<grid, 64, 0, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_fill_rows");
         }
         k_radius_fill<<<grid, 64, radius_lds_bytes(tab, true), s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");

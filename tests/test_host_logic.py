@@ -114,11 +114,11 @@ def test_stage_record_sums_the_stage_kernels(tmp_path):
     head = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
     rows_f = [(1, "__amd_rocclr_copyBuffer", half_kib / 2),  # counter reads half: scale 2
               (2, "sfc::k_radius_fill_rec(sfc::SearchArgs)", 100.0),
-              (3, "sfc::k_radius_fill_rec_long(sfc::SearchArgs)", 300.0),
+              (3, "sfc::k_radius_fill_rows(sfc::SearchArgs)", 300.0),
               (4, "sfc::k_radius_fill(sfc::SearchArgs)", 50.0),
               (5, "sfc::k_radius_count_rec(sfc::SearchArgs)", 1000.0)]
     rows_w = [(1, "__amd_rocclr_copyBuffer", half_kib), (2, "sfc::k_radius_fill_rec(sfc::SearchArgs)", 10.0),
-              (3, "sfc::k_radius_fill_rec_long(sfc::SearchArgs)", 30.0),
+              (3, "sfc::k_radius_fill_rows(sfc::SearchArgs)", 30.0),
               (4, "sfc::k_radius_fill(sfc::SearchArgs)", 0.0),
               (5, "sfc::k_radius_count_rec(sfc::SearchArgs)", 7.0)]
     f = tmp_path / "f.csv"
@@ -127,8 +127,8 @@ def test_stage_record_sums_the_stage_kernels(tmp_path):
     w.write_text(head + "".join(f"{d},\"{k}\",WRITE_SIZE,{v}\n" for d, k, v in rows_w))
     src = tmp_path / "s.hip"
     src.write_text("int x;\n")
-    r = stage_record(str(f), str(w), ["k_radius_fill_rec", "k_radius_fill_rec_long", "k_radius_fill"], 2, str(src))
+    r = stage_record(str(f), str(w), ["k_radius_fill_rec", "k_radius_fill_rows", "k_radius_fill"], 2, str(src))
     assert r["fetch_bytes_per_launch"] == (100.0 + 300.0 + 50.0) * 1024 * 2 / 2
     assert r["write_bytes_per_launch"] == (10.0 + 30.0) * 1024 / 2
     assert r["bytes_per_launch"] == r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]
-    assert r["fetch_bytes_by_kernel"]["k_radius_fill_rec_long"]["dispatches"] == 1
+    assert r["fetch_bytes_by_kernel"]["k_radius_fill_rows"]["dispatches"] == 1
