@@ -1508,10 +1508,10 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
 __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
+    if (!records_valid(a)) return;  // no records of this count (rec_n may be null): k_radius_fill searches every group
     const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
     if (v == kRecOverflow || (v & kRecLongRows)) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
-    if (!records_valid(a)) return;                   // k_radius_fill searches every group
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;  // empty rows
     radius_fill_rec_body(*reinterpret_cast<RecLds *>(g_radius_lds), a, C, g - C.g0,
@@ -1522,10 +1522,10 @@ __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
 __global__ __launch_bounds__(64) void k_radius_fill_rows(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
+    if (!records_valid(a)) return;
     const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
     if (v == kRecOverflow || !(v & kRecLongRows)) return;
     if (a.offsets[a.nq_total] > a.capacity) return;
-    if (!records_valid(a)) return;
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;
     radius_fill_rows_body(a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
