@@ -41,6 +41,7 @@
 // neighbourhoods and by VALU (candidate tests) for small ones.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <type_traits>
@@ -423,13 +424,20 @@ struct SearchCloud {
     int64_t q_offset;
     int64_t nq;
     int64_t g0;
+    int64_t rg0;    // its groups' record regions start here (regions exist only for recording clouds)
     float r;
     int32_t kernel;
     int32_t k;
     int32_t stage;  // radius search: points staged per round (64, 128, 256)
     int32_t rec;    // radius search: the cloud's hits are recorded (SFC_RECORD_HITS or the cloud's choice)
-    int64_t rg0;    // its groups' record regions start here (regions exist only for recording clouds)
 };
+// The host hashes table entries byte for byte up to `rec` (the records'
+// provenance tag): no padding may lie in between, since its bytes are
+// indeterminate and would make two identical calls hash differently.
+constexpr size_t kCloudHashBytes = offsetof(SearchCloud, rec) + sizeof(int32_t);
+static_assert(offsetof(SearchCloud, r) == 6 * sizeof(void *) + 5 * sizeof(int64_t) &&
+                  kCloudHashBytes == offsetof(SearchCloud, r) + 5 * sizeof(int32_t),
+              "SearchCloud has no padding before its end");
 
 struct SearchArgs {
     SearchCloud one;          // the cloud when tab is null
@@ -1440,9 +1448,19 @@ __global__ __launch_bounds__(64) void k_struct_fill(SearchArgs a) {
 
 namespace {
 
+// The record state the count kernel wrote, read through the device-coherent
+// vector path (uniform addresses would otherwise go through the scalar data
+// cache, which is only as fresh as its last invalidation).
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // do the workspace's records come from the count call this fill follows?
 __device__ __forceinline__ bool records_valid(const SearchArgs &a) {
-    return a.rec_tag && a.rec_tag[0] == a.tag0 && a.rec_tag[1] == a.tag1;
+    if (!a.rec_tag) return false;
+    const uint64_t t0 = coherent_load(a.rec_tag), t1 = coherent_load(a.rec_tag + 1);  // both loads in flight
+    return t0 == a.tag0 && t1 == a.tag1;
 }
 
 }  // namespace
@@ -1509,7 +1527,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_rec(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (!records_valid(a)) return;  // no records of this count (rec_n may be null): k_radius_fill searches every group
-    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    const uint32_t v = __builtin_amdgcn_readfirstlane(coherent_load(a.rec_n + g));
     if (v == kRecOverflow || (v & kRecLongRows)) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
     const SearchCloud C = group_cloud(a, g);
@@ -1523,7 +1541,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_rows(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (!records_valid(a)) return;
-    const uint32_t v = __builtin_amdgcn_readfirstlane(a.rec_n[g]);
+    const uint32_t v = __builtin_amdgcn_readfirstlane(coherent_load(a.rec_n + g));
     if (v == kRecOverflow || !(v & kRecLongRows)) return;
     if (a.offsets[a.nq_total] > a.capacity) return;
     const SearchCloud C = group_cloud(a, g);
@@ -1546,7 +1564,7 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
-    if (a.rec_n && records_valid(a) && a.rec_n[g] != kRecOverflow) return;  // written from its records
+    if (a.rec_n && records_valid(a) && coherent_load(a.rec_n + g) != kRecOverflow) return;  // written from its records
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.stage) {
@@ -2274,7 +2292,7 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
 
 void record_provenance(SearchArgs &a, const std::vector<SearchCloud> &tab, void *ws, uint64_t *tag, bool record) {
     uint64_t h = 0xcbf29ce484222325ull;
-    h = fnv1a(h, tab.data(), tab.size() * sizeof(SearchCloud));
+    for (const SearchCloud &c : tab) h = fnv1a(h, &c, kCloudHashBytes);
     const uintptr_t ptrs[4] = {reinterpret_cast<uintptr_t>(a.queries), reinterpret_cast<uintptr_t>(a.counts),
                                reinterpret_cast<uintptr_t>(a.offsets), static_cast<uintptr_t>(a.nq_total)};
     h = fnv1a(h, ptrs, sizeof ptrs);
