@@ -192,3 +192,62 @@ def test_record_fill_checks_provenance(sfc):
         _abi_call(sfc, t, "sphere", 1.0, ca, oa, idx, total, B.RECORD_HITS | B.REUSE_COUNTS, ws)
         torch.cuda.synchronize()
         assert_csr_equal((_np(ca), _np(oa), _np(idx)), ref, case)
+
+
+def test_record_long_rows_two_blocks(sfc):
+    """Long-row groups whose records exceed the 1024 the long-row fill holds
+    at once (a second block of records is loaded after the first block's
+    stores): a uniform cube where each group of 64 queries reaches 1000-2500
+    distinct points (records), all rows long."""
+    pts = datagen.uniform(20000, seed=17)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    c, o, idx = oracle.radius_search(pts, pts[perm], "sphere", 0.15)
+    # records of a group = the distinct points its queries find
+    recs = [np.unique(idx[o[g]:o[min(g + 64, c.size)]]).size for g in range(0, c.size, 64)]
+    assert max(recs) > 1024 and max(recs) <= 4096 and c.mean() >= 64
+    announce("record long rows, two record blocks")
+    _rec_case(sfc, pts, "hilbert", 32, "sphere", 0.15)
+
+
+def test_record_fill_shorter_rows(sfc):
+    """A fill given offsets with shorter rows than its count recorded (counts
+    changed by the caller between the calls) writes each row's first entries,
+    in the order the full fill writes them, and nothing past the new total:
+    every fill form (short rows at r = 0.5, long rows at r = 3)."""
+    import ctypes
+
+    import torch
+
+    from paper_2603_06771_amd import _binding as B
+    pts = datagen.lidar_tile(40000, seed=33)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
+    n = pts.shape[0]
+    L = B.load()
+    need = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(256)
+    B.check(L.radius_search(ctypes.byref(t.view), None, n, 0, 1.0, fake, fake, None, 0, B.RECORD_HITS, None,
+                            ctypes.byref(need), None), "size")
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    for r in (0.5, 3.0):
+        announce(f"record fill, shorter rows, r={r}")
+        full = sfc.radius_search(t, None, "sphere", r)
+        torch.cuda.synchronize()
+        fc, fo, fi = (_np(x) for x in full)
+        counts = torch.empty(n, dtype=torch.int32, device="cuda")
+        offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        _abi_call(sfc, t, "sphere", r, counts, offsets, None, 0, B.RECORD_HITS, ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(counts), fc)
+        short = (fc // 2).astype(np.int32)
+        so = np.concatenate([[0], np.cumsum(short, dtype=np.int64)])
+        counts.copy_(torch.from_numpy(short))
+        offsets.copy_(torch.from_numpy(so))
+        total = int(so[-1])
+        idx = torch.full((total + 4096,), -1, dtype=torch.int32, device="cuda")
+        _abi_call(sfc, t, "sphere", r, counts, offsets, idx, total, B.RECORD_HITS | B.REUSE_COUNTS, ws)
+        torch.cuda.synchronize()
+        got = _np(idx)
+        assert np.all(got[total:] == -1), "entries written past the new total"
+        want = np.concatenate([fi[fo[i]:fo[i] + short[i]] for i in range(n)])
+        assert np.array_equal(got[:total], want), "rows are not the full rows' prefixes"
