@@ -1046,11 +1046,12 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
 // records of nearly every long-row group, so the wave loads nothing after its
 // first store: on this GPU a wait for a load also waits for every store
 // issued before it).  For each query the lanes whose record mask holds its
-// bit store their original index at the row's next positions (each lane's
+// bit put their original index at the row's next positions (each lane's
 // rank among them from mbcnt, which also adds the entries already written).
-// A group's rows are consecutive in the output, so its stores run through
-// one region in order; a record chunk costs a query five vector
-// instructions and one store, whatever its hits.
+// A group of a cloud's own points has its rows consecutive in the output, so
+// the pieces fill one region in order: they go to an LDS buffer written out
+// 256 entries at a time with 16-byte stores; other groups store each piece
+// straight to its row.
 constexpr int kRowBlk = SFC_REC_ROWBLK;
 static_assert(kRowBlk >= 1 && kRowBlk <= 16, "record chunks held per pass");
 
@@ -1075,33 +1076,14 @@ __device__ __forceinline__ void rows_queries(uint64_t qm, const uint32_t (&word)
             tot += static_cast<uint32_t>(__popcll(m[u]));
         }
         uint32_t *const row = out + readlane_u64(start, j);
-        if (w + tot <= rl) {  // always, when the offsets come from this count
-            // every chunk's byte offsets in a register of its own, all computed
-            // before the first store (none sunk into the predicated store
-            // blocks, where one register would serve them all and each
-            // offset would wait for the previous store to release it)
-            uint32_t off[NCH];
-            uint32_t at = w;
+        const bool whole = w + tot <= rl;  // always, when the offsets come from this count
+        uint32_t at = w;
 #pragma unroll
-            for (int u = 0; u < NCH; ++u) {
-                off[u] = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), at)) * 4u;
-                at += static_cast<uint32_t>(__popcll(m[u]));
-            }
-#pragma unroll
-            for (int u = 0; u < NCH; ++u) asm volatile("" : "+v"(off[u]));
-#pragma unroll
-            for (int u = 0; u < NCH; ++u)
-                if (__builtin_amdgcn_inverse_ballot_w64(m[u]))
-                    *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(row) + off[u]) = pi[u];
-        } else {  // a shorter row (offsets not from this count) takes the first of its entries
-            uint32_t at = w;
-#pragma unroll
-            for (int u = 0; u < NCH; ++u) {
-                const uint32_t pos = at + rank_below(m[u]);
-                if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && pos < rl) row[pos] = pi[u];
-                at += static_cast<uint32_t>(__popcll(m[u]));
-            }
+        for (int u = 0; u < NCH; ++u) {
+            const uint32_t pos = at + rank_below(m[u]);
+            // a shorter row (offsets not from this count) takes the first of its entries
+            if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && (whole || pos < rl)) row[pos] = pi[u];
+            at += static_cast<uint32_t>(__popcll(m[u]));
         }
         done = writelane_u32(w + tot, j, done);
     }
@@ -1122,8 +1104,95 @@ __device__ __forceinline__ void rows_block(int nch, uint64_t rows, const uint32_
     rows_queries<NCH>(rows & ~0xFFFFFFFFull, hi, pi, start, len, done, out);
 }
 
+// Staged long rows, for a group whose records fit one block and whose rows
+// are consecutive in lane order (then its output is one region [r0, r1),
+// written strictly in order): pieces go to an LDS buffer of kRowBuf entries
+// that starts at `base` (a multiple of 4 entries); every 256 entries are
+// written out as one 16-byte store per lane, so the wave issues a quarter of
+// the stores at whole cache lines.  `front` is the end of what the pieces
+// wrote so far.
+constexpr int kRowBuf = 320;  // 256 written out at a time + up to 63 carried over
+struct RowStage {
+    uint32_t *buf;  // LDS, kRowBuf entries, 16-byte aligned
+    uint32_t *out;  // the output indices, 16-byte aligned
+    uint64_t r0, r1, base, front;
+};
+
+// Writes out entries [st.base, st.base + 256) that lie in [r0, r1) and moves
+// those past them (fewer than 64, up to st.front) to the buffer's start.
+__device__ __forceinline__ void stage_flush(RowStage &st) {
+    const int lane = lane_id();
+    const uint64_t g0 = st.base + 4u * static_cast<uint32_t>(lane);
+    const uint4 v = *reinterpret_cast<const uint4 *>(st.buf + 4 * lane);
+    if (g0 >= st.r0 && g0 + 4 <= st.r1) {
+        *reinterpret_cast<uint4 *>(st.out + g0) = v;
+    } else {
+        const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (g0 + i >= st.r0 && g0 + i < st.r1) st.out[g0 + i] = e[i];
+    }
+    const uint64_t end = st.base + 256;
+    const uint32_t mv = st.front > end ? static_cast<uint32_t>(min<uint64_t>(st.front - end, kWave)) : 0u;
+    uint32_t t = 0;
+    if (static_cast<uint32_t>(lane) < mv) t = st.buf[256 + lane];
+    wave_sync();
+    if (static_cast<uint32_t>(lane) < mv) st.buf[lane] = t;
+    wave_sync();
+    st.base = end;
+}
+
+template <int NCH>
+__device__ __forceinline__ void rows_queries_staged(uint64_t qm, const uint32_t (&word)[kRowBlk],
+                                                    const uint32_t (&pi)[kRowBlk], uint64_t start, uint32_t len,
+                                                    RowStage &st) {
+    for (; qm; qm &= qm - 1) {
+        const int j = __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(qm)) - 1);
+        const uint32_t rl = readlane_u32(len, j);
+        const uint64_t s0 = readlane_u64(start, j);
+        const uint32_t bit = 1u << (j & 31);
+        // rows between (longer than their records) are skipped over
+        while (s0 >= st.base + 256) stage_flush(st);
+        uint64_t m[NCH];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            m[u] = ballot((word[u] & bit) != 0u);
+            tot += static_cast<uint32_t>(__popcll(m[u]));
+        }
+        const bool whole = tot <= rl;  // always, when the offsets come from this count
+        uint32_t at = 0;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            // the piece's buffer position: below 256 while at <= rl (a flush
+            // follows every piece that reaches 256), so rel + rank < kRowBuf
+            const uint32_t rel = static_cast<uint32_t>(s0 - st.base) + at;
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), rel));
+            if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && (whole || at + (pos - rel) < rl)) st.buf[pos] = pi[u];
+            at += static_cast<uint32_t>(__popcll(m[u]));
+            st.front = s0 + min(at, rl);
+            if (st.front >= st.base + 256) stage_flush(st);
+        }
+    }
+}
+
+template <int NCH = kRowBlk>
+__device__ __forceinline__ void rows_block_staged(int nch, uint64_t rows, const uint32_t (&lo)[kRowBlk],
+                                                  const uint32_t (&hi)[kRowBlk], const uint32_t (&pi)[kRowBlk],
+                                                  uint64_t start, uint32_t len, RowStage &st) {
+    if constexpr (NCH > 1) {
+        if (nch < NCH) {
+            rows_block_staged<NCH - 1>(nch, rows, lo, hi, pi, start, len, st);
+            return;
+        }
+    }
+    rows_queries_staged<NCH>(rows & 0xFFFFFFFFull, lo, pi, start, len, st);
+    rows_queries_staged<NCH>(rows & ~0xFFFFFFFFull, hi, pi, start, len, st);
+}
+
 __device__ __forceinline__ void radius_fill_rows_body(const SearchArgs &a, const SearchCloud &C, int64_t lg,
-                                                      uint32_t n) {
+                                                      uint32_t n, uint32_t *stage_buf) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
     int64_t row;
@@ -1137,6 +1206,38 @@ __device__ __forceinline__ void radius_fill_rows_body(const SearchArgs &a, const
     const uint64_t rows = ballot(len > 0);
     const uint32_t *ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
     const uint64_t *rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
+    // one block, rows consecutive in lane order, output 16-byte aligned: staged
+    const int64_t row0 = readlane_u64(static_cast<uint64_t>(row), 0);
+    const bool consecutive = ballot(q.valid && row != row0 + lane) == 0ull;
+    if (n <= static_cast<uint32_t>(kRowBlk * kWave) && consecutive &&
+        (reinterpret_cast<uintptr_t>(a.indices) & 15u) == 0 && rows) {
+        uint32_t pi[kRowBlk], lo[kRowBlk], hi[kRowBlk];
+#pragma unroll
+        for (int u = 0; u < kRowBlk; ++u) {
+            const uint32_t k = u * kWave + lane;
+            const bool have = k < n;
+            const uint64_t pm = have ? rmask[k] : 0ull;
+            pi[u] = have ? ridx[k] : 0u;
+            lo[u] = static_cast<uint32_t>(pm);
+            hi[u] = static_cast<uint32_t>(pm >> 32);
+        }
+        RowStage st;
+        st.buf = stage_buf;
+        st.out = a.indices;
+        const int last = 63 - __clzll(static_cast<long long>(ballot(q.valid)));
+        st.r0 = readlane_u64(start, 0);
+        st.r1 = readlane_u64(start + len, last);
+        st.base = st.r0 & ~3ull;
+        st.front = st.r0;
+        const int nch = static_cast<int>(min((n + kWave - 1) / kWave, static_cast<uint32_t>(kRowBlk)));
+        rows_block_staged(nch, rows, lo, hi, pi, start, len, st);
+        while (st.base < st.r1) {
+            st.front = st.r1;
+            stage_flush(st);
+        }
+        return;
+    }
+    // otherwise each piece is stored straight to its row
     for (uint32_t b0 = 0; b0 < n; b0 += kRowBlk * kWave) {
         uint32_t pi[kRowBlk], lo[kRowBlk], hi[kRowBlk];
 #pragma unroll
@@ -1546,7 +1647,8 @@ __global__ __launch_bounds__(64) void k_radius_fill_rows(SearchArgs a) {
     if (a.offsets[a.nq_total] > a.capacity) return;
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;
-    radius_fill_rows_body(a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)));
+    __shared__ __align__(16) uint32_t stage_buf[kRowBuf];
+    radius_fill_rows_body(a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)), stage_buf);
 }
 
 template <int STAGE>
