@@ -2,7 +2,10 @@
 
 Device flags: no fp contraction (every fp32 expression evaluated as written),
 denormals kept, correctly rounded fp32 division, packed-fp32 instructions
-disabled.  The library is built in-tree, next to this file.
+disabled.  The library is built in-tree, next to this file.  Beside it,
+libsfcoct_stats.so is the same library with the count kernels' sweep
+statistics compiled in (SFC_SWEEP_STATS: tests and hits per search, read by
+sweep_stats.py); the search results are the same.
 """
 from __future__ import annotations
 
@@ -15,6 +18,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfcoct.so")
+STATS_LIB = os.path.join(HERE, "libsfcoct_stats.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -32,16 +36,20 @@ def sources():
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every .hip source and link libsfcoct.so (always rebuilds)."""
+    """Compile every .hip source and link libsfcoct.so and libsfcoct_stats.so
+    (always rebuilds); returns the path of libsfcoct.so."""
     objdir = tempfile.mkdtemp(prefix="sfcoct_build_")
-    procs, objs = [], []
-    for src in sources():
-        obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    # (source, extra flags, object); search.hip a second time for the statistics build
+    jobs_list = [(src, [], os.path.join(objdir, os.path.basename(src) + ".o")) for src in sources()]
+    search = [src for src in sources() if os.path.basename(src) == "search.hip"]
+    stats_obj = os.path.join(objdir, "search_stats.hip.o")
+    jobs_list += [(src, ["-DSFC_SWEEP_STATS"], stats_obj) for src in search]
+    procs = []
+    for src, extra, obj in jobs_list:
+        cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
         while len([p for _, p in procs if p.poll() is None]) >= jobs:
             procs[0][1].wait()
     failed = []
@@ -53,14 +61,17 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             failed.append(src)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    for o in objs:
-        os.remove(o)
+    plain = [obj for _, extra, obj in jobs_list if not extra]
+    stats = [obj for obj in plain if os.path.basename(obj) != "search.hip.o"] + [stats_obj]
+    for lib, objs in ((LIB, plain), (STATS_LIB, stats)):
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, lib)
+    for _, _, obj in jobs_list:
+        os.remove(obj)
     os.rmdir(objdir)
     return LIB
 

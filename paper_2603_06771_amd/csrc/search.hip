@@ -805,6 +805,24 @@ __device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, con
     return node;
 }
 
+#ifdef SFC_SWEEP_STATS
+// Sweep statistics of the count kernels (a separate build, libsfcoct_stats.so:
+// the search itself is unchanged), summed over every group since the last
+// reset: [0] point tests (staged points swept x the group's valid queries),
+// [1] neighbours found, [2] groups, [3] staged points swept; [4..7] the same
+// for recording groups only.
+__device__ unsigned long long g_sweep_stats[8];
+
+__device__ __forceinline__ void sweep_stats_add(uint32_t swept, int nvalid, uint32_t hits, bool rec) {
+    if (lane_id() != 0) return;
+    unsigned long long *s = g_sweep_stats + (rec ? 4 : 0);
+    atomicAdd(s + 0, static_cast<unsigned long long>(swept) * static_cast<unsigned long long>(nvalid));
+    atomicAdd(s + 1, static_cast<unsigned long long>(hits));
+    atomicAdd(s + 2, 1ull);
+    atomicAdd(s + 3, static_cast<unsigned long long>(swept));
+}
+#endif
+
 // With REC (SFC_RECORD_HITS) the wave also records, per staged point that
 // is a neighbour of at least one of its queries, the point's original index
 // and the mask of those queries, in staging order, into the group's region
@@ -834,10 +852,12 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         return;
     }
     uint32_t nrec = 0;  // records of the group so far (may pass kRecCap: then none is kept)
+    uint32_t swept = 0;  // staged points every lane tested (the sweep statistics)
     if (r > 0.0f) {
         // every lane tests its query against the staged points
         auto body = [&](uint32_t n_) {
             const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
+            swept += n;
             uint32_t t = 0;
             for (; t + 4 <= n; t += 4) {
                 const float4 p0 = L.pts[t], p1 = L.pts[t + 1], p2 = L.pts[t + 2], p3 = L.pts[t + 3];
@@ -856,6 +876,7 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         uint64_t *const rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
         auto body_rec = [&](uint32_t n_) {
             const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
+            swept += n;
             for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
                 const uint32_t te = min(n, t0 + kWave);
                 uint32_t mlo = 0, mhi = 0;
@@ -920,6 +941,11 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         }
     }
     if (q.valid) a.counts[row] = cnt;
+#ifdef SFC_SWEEP_STATS
+    sweep_stats_add(swept, __popcll(ballot(q.valid)), wave_sum_u(q.valid ? cnt : 0u), REC);
+#else
+    (void)swept;
+#endif
     if constexpr (REC) {
         // groups whose rows average kRecLongMean entries or more take the long-row form
         const uint32_t hits = __shfl(wave_inclusive_sum(q.valid ? cnt : 0u), kWave - 1);
@@ -2834,3 +2860,25 @@ extern "C" int radius_search_noalloc(const sfc_octree *tree, const float *querie
     size_t have = kScratchBytes;
     return radius_search(tree, queries, nq, kernel, r, counts, offsets, indices, capacity, flags, ws, &have, stream);
 }
+
+#ifdef SFC_SWEEP_STATS
+// Copies the count kernels' sweep statistics (see g_sweep_stats) to out[8]
+// and, with reset != 0, clears them; synchronizes the device.
+extern "C" int sfc_sweep_stats(unsigned long long *out, int reset) {
+    if (!out) {
+        set_error("sfc_sweep_stats: null output");
+        return SFC_EINVAL;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(sfc::g_sweep_stats));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(out, p, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemset(p, 0, sizeof(unsigned long long) * 8);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        set_error("sfc_sweep_stats: %s", hipGetErrorString(e));
+        return SFC_EHIP;
+    }
+    return SFC_OK;
+}
+#endif
