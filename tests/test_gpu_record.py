@@ -251,3 +251,46 @@ def test_record_fill_shorter_rows(sfc):
         assert np.all(got[total:] == -1), "entries written past the new total"
         want = np.concatenate([fi[fo[i]:fo[i] + short[i]] for i in range(n)])
         assert np.array_equal(got[:total], want), "rows are not the full rows' prefixes"
+
+
+def test_record_rows_ordered_external_and_unaligned(sfc):
+    """The long-row fill's staged path (rows consecutive in lane order,
+    16-byte aligned output) and its direct path (otherwise): external queries
+    already in curve order (SFC_QUERIES_ORDERED: rows consecutive, staged),
+    the same queries with the output at an address 4 bytes past a 16-byte
+    boundary (direct), against the search fill entry for entry."""
+    import ctypes
+
+    import torch
+
+    from paper_2603_06771_amd import _binding as B
+    pts = datagen.lidar_tile(40000, seed=35)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    q = _dev(pts[perm][::3].copy())  # every third point, in curve order
+    nq = q.shape[0]
+    L = B.load()
+    for kernel, r in (("sphere", 3.0), ("cube", 2.5)):
+        base = sfc.radius_search(t, q, kernel, r)
+        torch.cuda.synchronize()
+        bc, bo, bi = (_np(x) for x in base)
+        total = int(bo[-1])
+        counts = torch.empty(nq, dtype=torch.int32, device="cuda")
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+        call = (ctypes.byref(t.view), ctypes.c_void_p(q.data_ptr()), nq, sfc.KERNELS[kernel], r,
+                ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(offsets.data_ptr()))
+        flags = B.RECORD_HITS | B.QUERIES_ORDERED
+        need = ctypes.c_size_t(0)
+        B.check(L.radius_search(*call, None, 0, flags, None, ctypes.byref(need), None), "size")
+        ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for shift in (0, 1):  # entries: 0 keeps the buffer's 256-byte alignment, 1 is 4 bytes past it
+            announce(f"record rows, ordered external queries, {kernel} r={r}, output shift {shift}")
+            buf = torch.full((total + 8,), -1, dtype=torch.int32, device="cuda")
+            B.check(L.radius_search(*call, ctypes.c_void_p(buf.data_ptr() + 4 * shift), total, flags,
+                                    ctypes.c_void_p(ws.data_ptr()), ctypes.byref(need), s), "radius_search")
+            torch.cuda.synchronize()
+            got = _np(buf)
+            assert np.array_equal(_np(counts), bc) and np.array_equal(_np(offsets), bo)
+            assert np.all(got[:shift] == -1) and np.all(got[shift + total:] == -1)
+            assert np.array_equal(got[shift:shift + total], bi[:total]), f"{kernel} r={r} shift {shift}"
