@@ -472,6 +472,7 @@ struct SearchArgs {
     // of the call's arguments), else it searches again
     uint64_t *rec_tag;
     uint64_t tag0, tag1;
+    uint32_t fill_scan;       // k_radius_fill: every group recorded, kFillScan groups per wave
 };
 
 // Query of a lane (position lr in its cloud's rows) and the global row its
@@ -1688,11 +1689,7 @@ __device__ __forceinline__ void radius_fill_tile(const SearchArgs &a, const Sear
     }
 }
 
-__global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
-    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= a.groups) return;
-    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
-    if (a.rec_n && records_valid(a) && coherent_load(a.rec_n + g) != kRecOverflow) return;  // written from its records
+__device__ __forceinline__ void radius_fill_group(const SearchArgs &a, int64_t g) {
     const SearchCloud C = group_cloud(a, g);
     const int64_t lg = g - C.g0;
     switch (C.stage) {
@@ -1700,6 +1697,33 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
     case 256: radius_fill_tile<256>(a, C, lg); break;
     default: radius_fill_tile<128>(a, C, lg); break;
     }
+}
+
+// One wave per group; or, when every cloud of the launch records its hits
+// (a.fill_scan), one wave per kFillScan groups that picks out the groups
+// whose records overflowed and serves them in turn: a search with none costs
+// an eighth of the waves, one where all overflow at most 8 groups in a row
+// per wave.
+constexpr int kFillScan = 8;
+
+__global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
+    if (a.fill_scan) {
+        const int64_t g0 = xcd_item(blockIdx.x, gridDim.x) * kFillScan;
+        if (g0 >= a.groups) return;
+        if (a.offsets[a.nq_total] > a.capacity) return;
+        const bool valid = records_valid(a);  // else every group is searched
+        const int64_t g = g0 + lane_id();
+        const bool need = lane_id() < kFillScan && g < a.groups &&
+                          (!valid || coherent_load(a.rec_n + g) == kRecOverflow);
+        for (uint64_t m = ballot(need); m; m &= m - 1)
+            radius_fill_group(a, g0 + __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(m)) - 1));
+        return;
+    }
+    const int64_t g = xcd_item(blockIdx.x, gridDim.x);
+    if (g >= a.groups) return;
+    if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
+    if (a.rec_n && records_valid(a) && coherent_load(a.rec_n + g) != kRecOverflow) return;  // written from its records
+    radius_fill_group(a, g);
 }
 
 // Deferred (spread) groups: one wave per query, grid-stride over the list.
@@ -2505,7 +2529,11 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
             k_radius_fill_rows<<<grid, 64, 0, s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_fill_rows");
         }
-        k_radius_fill<<<grid, 64, radius_lds_bytes(tab, true), s>>>(a);
+        // every group recorded: the search fill only looks for overflowed ones
+        a.fill_scan = record && rec_groups == groups ? 1u : 0u;
+        const unsigned fgrid =
+            a.fill_scan ? static_cast<unsigned>(xcd_grid((groups + kFillScan - 1) / kFillScan)) : grid;
+        k_radius_fill<<<fgrid, 64, radius_lds_bytes(tab, true), s>>>(a);
         SFC_LAUNCH_CHECK("k_radius_fill");
         if (a.queries) {
             k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
