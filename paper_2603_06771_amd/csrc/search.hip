@@ -806,13 +806,46 @@ __device__ __forceinline__ int start_node(const Lds &L, const SearchArgs &a, con
     return node;
 }
 
+// Shader-clock time of the count's phases per wave, in the statistics build
+// only (elsewhere every call compiles to nothing): [0] segments, [1] start
+// node, [2] walk (traversal alone), [3] classification, [4] staging (without
+// the tests), [5] tests, [6] the rest (the last tests and the epilogue).
+struct PhaseClock {
+#ifdef SFC_SWEEP_STATS
+    unsigned long long t[7] = {};
+    unsigned long long tests_before_tail = 0;
+    __device__ __forceinline__ static unsigned long long now() { return __builtin_amdgcn_s_memtime(); }
+    __device__ __forceinline__ void add(int i, unsigned long long t0) { t[i] += now() - t0; }
+    __device__ __forceinline__ void mark_tail() { tests_before_tail = t[5]; }
+    // the walk's time holds the sweeps', a sweep's holds its classification
+    // and tests, and the tail's its last tests: take each nested phase out
+    __device__ __forceinline__ void nest() {
+        const unsigned long long tail_tests = t[5] - tests_before_tail;
+        t[6] -= tail_tests;
+        t[2] -= t[4];
+        t[4] -= t[3] + tests_before_tail;
+    }
+#else
+    __device__ __forceinline__ static unsigned long long now() { return 0ull; }
+    __device__ __forceinline__ void add(int, unsigned long long) {}
+    __device__ __forceinline__ void mark_tail() {}
+#endif
+};
+
 #ifdef SFC_SWEEP_STATS
 // Sweep statistics of the count kernels (a separate build, libsfcoct_stats.so:
 // the search itself is unchanged), summed over every group since the last
 // reset: [0] point tests (staged points swept x the group's valid queries),
 // [1] neighbours found, [2] groups, [3] staged points swept; [4..7] the same
-// for recording groups only.
-__device__ unsigned long long g_sweep_stats[8];
+// for recording groups only; [8..14] the phase clocks (PhaseClock), [15]
+// the whole body's clock.
+__device__ unsigned long long g_sweep_stats[16];
+
+__device__ __forceinline__ void sweep_clock_add(const PhaseClock &pc, unsigned long long total) {
+    if (lane_id() != 0) return;
+    for (int i = 0; i < 7; ++i) atomicAdd(g_sweep_stats + 8 + i, pc.t[i]);
+    atomicAdd(g_sweep_stats + 15, total);
+}
 
 __device__ __forceinline__ void sweep_stats_add(uint32_t swept, int nvalid, uint32_t hits, bool rec) {
     if (lane_id() != 0) return;
@@ -844,6 +877,8 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
     const int64_t gg = lg + C.g0;  // global group
     uint32_t cnt = 0;
     int sid = 0;
+    PhaseClock pc;
+    const unsigned long long t_begin = PhaseClock::now();
     const int nseg = r > 0.0f ? make_segments(L, q, 2.0f * r, &sid, kJumpSteps) : 0;
     if (r > 0.0f && may_defer(a) && spread_group(L, nseg, r, __popcll(ballot(q.valid)))) {
         if constexpr (REC) {
@@ -852,11 +887,13 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         defer_group(a, gg);
         return;
     }
+    pc.add(0, t_begin);
     uint32_t nrec = 0;  // records of the group so far (may pass kRecCap: then none is kept)
     uint32_t swept = 0;  // staged points every lane tested (the sweep statistics)
     if (r > 0.0f) {
         // every lane tests its query against the staged points
         auto body = [&](uint32_t n_) {
+            const unsigned long long t_body = PhaseClock::now();
             const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
             swept += n;
             uint32_t t = 0;
@@ -868,6 +905,7 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
                 cnt += point_hit<KERNEL>(p3, q.x, q.y, q.z, r, r2) ? 1u : 0u;
             }
             for (; t < n; ++t) cnt += point_hit<KERNEL>(L.pts[t], q.x, q.y, q.z, r, r2) ? 1u : 0u;
+            pc.add(5, t_body);
         };
         // recording: lane j of (mlo, mhi) takes the query mask of staged point
         // t0 + j; per 64 points the ones with a neighbour are compacted and
@@ -876,6 +914,7 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         uint32_t *const ridx = a.rec_idx + (C.rg0 + lg) * kRecCap;
         uint64_t *const rmask = a.rec_mask + (C.rg0 + lg) * kRecCap;
         auto body_rec = [&](uint32_t n_) {
+            const unsigned long long t_body = PhaseClock::now();
             const uint32_t n = __builtin_amdgcn_readfirstlane(n_);
             swept += n;
             for (uint32_t t0 = 0; t0 < n; t0 += kWave) {
@@ -907,6 +946,7 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
                 }
                 nrec += static_cast<uint32_t>(__popcll(km));
             }
+            pc.add(5, t_body);
         };
         uint32_t staged = 0;  // points staged and not yet swept, across candidate batches
         // Once the records overflow the group is left to the search fill, so
@@ -915,11 +955,14 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
         auto recording = [&]() { return REC && nrec <= static_cast<uint32_t>(kRecCap); };
         auto accept = [&](const sfc_node &nd) { return segments_may_hit<KERNEL>(L, nseg, nd, r, r2); };
         auto sweep = [&](int ncand) {
+            const unsigned long long t_sweep = PhaseClock::now();
             for (int c0 = 0; c0 < ncand; c0 += kWave) {
                 const int m = min(kWave, ncand - c0);
                 uint64_t mixed, touched, full;
+                const unsigned long long t_cls = PhaseClock::now();
                 const uint32_t len =
                     classify_segments<KERNEL>(L, C.nodes, c0, m, nseg, sid, r, r2, prune, &mixed, &touched, &full);
+                pc.add(3, t_cls);
                 if (recording()) {
                     if (!touched) continue;
                     stage_union<KERNEL>(L, C.pts, c0, m, touched, len, nseg, r, r2, body_rec, &staged);
@@ -931,8 +974,16 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
                     stage_union<KERNEL>(L, C.pts, c0, m, mixed, len, nseg, r, r2, body, &staged);
                 }
             }
+            pc.add(4, t_sweep);  // the sweep's whole time; classification and tests are taken out below
         };
-        traverse(L, C.nodes, C.child, accept, sweep, start_node<KERNEL>(L, a, C, nseg, r, q, lr));
+        const unsigned long long t_start = PhaseClock::now();
+        const int start = start_node<KERNEL>(L, a, C, nseg, r, q, lr);
+        pc.add(1, t_start);
+        const unsigned long long t_walk = PhaseClock::now();
+        traverse(L, C.nodes, C.child, accept, sweep, start);
+        pc.add(2, t_walk);  // the walk's whole time; the sweeps are taken out below
+        pc.mark_tail();
+        const unsigned long long t_tail = PhaseClock::now();
         if (staged) {
             wave_sync();
             if (recording())
@@ -940,10 +991,13 @@ __device__ __forceinline__ void radius_count_body(RadLdsT<STAGE> &L, const Searc
             else
                 body(staged);
         }
+        pc.add(6, t_tail);
     }
     if (q.valid) a.counts[row] = cnt;
 #ifdef SFC_SWEEP_STATS
     sweep_stats_add(swept, __popcll(ballot(q.valid)), wave_sum_u(q.valid ? cnt : 0u), REC);
+    pc.nest();
+    sweep_clock_add(pc, PhaseClock::now() - t_begin);
 #else
     (void)swept;
 #endif
@@ -2890,7 +2944,7 @@ extern "C" int radius_search_noalloc(const sfc_octree *tree, const float *querie
 }
 
 #ifdef SFC_SWEEP_STATS
-// Copies the count kernels' sweep statistics (see g_sweep_stats) to out[8]
+// Copies the count kernels' sweep statistics (see g_sweep_stats) to out[16]
 // and, with reset != 0, clears them; synchronizes the device.
 extern "C" int sfc_sweep_stats(unsigned long long *out, int reset) {
     if (!out) {
@@ -2900,8 +2954,8 @@ extern "C" int sfc_sweep_stats(unsigned long long *out, int reset) {
     void *p = nullptr;
     hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(sfc::g_sweep_stats));
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(out, p, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && reset) e = hipMemset(p, 0, sizeof(unsigned long long) * 8);
+    if (e == hipSuccess) e = hipMemcpy(out, p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemset(p, 0, sizeof(unsigned long long) * 16);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         set_error("sfc_sweep_stats: %s", hipGetErrorString(e));

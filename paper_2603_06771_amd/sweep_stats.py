@@ -10,7 +10,9 @@ plain count.
 
 It needs libsfcoct_stats.so (built beside libsfcoct.so by build.py), the same
 kernels with counters that sum, over every group, the staged points it swept
-times its valid queries and the neighbours it counted.
+times its valid queries and the neighbours it counted, and the shader-clock
+time of each phase of a group's work (segments, start node, walk,
+classification, staging, tests, the rest), as shares of the total.
 
     python -m paper_2603_06771_amd.sweep_stats [--points N] [--leaf L]
 """
@@ -47,11 +49,12 @@ def main() -> None:
     counts = torch.empty(n, dtype=torch.int32, device="cuda")
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    out = (ctypes.c_ulonglong * 8)()
+    out = (ctypes.c_ulonglong * 16)()
     B.check(L.sfc_sweep_stats(out, 1), "sfc_sweep_stats")
     rows = []
+    phases = ("segments", "start", "walk", "classify", "staging", "tests", "rest")
     print(f"{'curve':8s} {'kernel':7s} {'r':>4s} {'count':6s} {'mu':>7s} {'tests/hit':>9s} {'tests/query':>11s} "
-          f"{'staged/group':>12s}", flush=True)
+          f"{'staged/group':>12s}  phase shares (%): " + " ".join(f"{p:>8s}" for p in phases), flush=True)
     for curve in ("morton", "hilbert"):
         tree = sfc.build_linear_octree(xyz, curve, 21, args.leaf)
         for kernel in ("sphere", "cube"):
@@ -67,15 +70,19 @@ def main() -> None:
                             "radius_search(count)")
                     B.check(L.sfc_sweep_stats(out, 1), "sfc_sweep_stats")
                     del ws
-                    s = list(out)[4:] if record else list(out)[:4]
+                    s = list(out)[4:8] if record else list(out)[:4]
                     tests, hits, groups, swept = s
+                    clock = list(out)[8:15]
+                    total = max(list(out)[15], 1)
                     row = {"curve": curve, "kernel": kernel, "r": r, "count": "record" if record else "plain",
                            "mu": hits / n, "tests_per_hit": tests / max(hits, 1), "tests_per_query": tests / n,
-                           "staged_per_group": swept / max(groups, 1), "groups": groups}
+                           "staged_per_group": swept / max(groups, 1), "groups": groups,
+                           "phase_share": {p: c / total for p, c in zip(phases, clock)}}
                     rows.append(row)
                     print(f"{curve:8s} {kernel:7s} {r:4.1f} {row['count']:6s} {row['mu']:7.1f} "
                           f"{row['tests_per_hit']:9.2f} {row['tests_per_query']:11.1f} "
-                          f"{row['staged_per_group']:12.1f}", flush=True)
+                          f"{row['staged_per_group']:12.1f}                    " +
+                          " ".join(f"{100 * row['phase_share'][p]:8.1f}" for p in phases), flush=True)
         del tree
     if args.json:
         with open(args.json, "w") as f:

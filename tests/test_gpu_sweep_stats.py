@@ -25,7 +25,7 @@ def test_sweep_stats_consistent():
     n = pts.shape[0]
     counts = torch.empty(n, dtype=torch.int32, device="cuda")
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-    out = (ctypes.c_ulonglong * 8)()
+    out = (ctypes.c_ulonglong * 16)()
     assert S.sfc_sweep_stats(out, 1) == 0
     for kernel, r in (("sphere", 0.5), ("cube", 3.0)):
         for flags in (B.RECORD_HITS, 0):
@@ -39,7 +39,8 @@ def test_sweep_stats_consistent():
                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
             assert S.sfc_sweep_stats(out, 1) == 0
             s = np.array(list(out), dtype=np.int64)
-            tests, hits, groups, swept = s[4:] if flags else s[:4]
+            tests, hits, groups, swept = s[4:8] if flags else s[:4]
             ref = sfc.radius_count(t, None, kernel, r)[1][-1].item()
             assert hits == ref and groups == (n + 63) // 64 and tests >= hits and swept > 0
-            assert not (s[:4] if flags else s[4:]).any()  # only one kind of count ran
+            assert not (s[:4] if flags else s[4:8]).any()  # only one kind of count ran
+            assert s[15] > 0 and s[8:15].sum() <= s[15]  # phase clocks within the whole
