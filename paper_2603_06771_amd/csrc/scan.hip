@@ -1,16 +1,19 @@
-// Device-wide exclusive prefix sum of uint32 counts (reduce-then-scan):
-//   k_scan_tiles : each block scans a tile of 2048 counts locally and records
-//                  the tile total
-//   k_scan_sums  : one block scans the tile totals
-//   k_scan_add   : tiles add their offset; the grand total goes to out[n]
-// Used for CSR row offsets, radix-sort digit offsets and node emission.
+// Device-wide exclusive prefix sum of uint32 counts (reduce-then-scan, each
+// count read twice and each offset written once):
+//   k_scan_reduce : each block sums a tile of kScanTile counts
+//   k_scan_sums   : one block scans the tile totals (exclusive, grand total last)
+//   k_scan_down   : each block scans its tile again, from its tile's offset,
+//                   and writes the offsets; the grand total goes to out[n]
+// Used for CSR row offsets, radix-sort digit offsets and node emission.  The
+// input and output may be the same array (every item is read before the
+// thread that reads it writes it).
 #include "internal.hpp"
 
 namespace sfc {
 
 namespace {
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
 template <typename T>
@@ -29,27 +32,23 @@ __device__ T block_exclusive_sum(T v, T *s_wave, T *total) {
     *total = all;
     return wave_off + incl - v;
 }
+
+// thread t of a block holds items [base + t * kScanItems, ... + kScanItems)
+__device__ __forceinline__ int64_t item_base(int64_t block) {
+    return block * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
+}
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const uint32_t *__restrict__ in, int64_t n,
-                                                           T *__restrict__ out, T *__restrict__ sums) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                            T *__restrict__ sums) {
     __shared__ T s_wave[kScanBlock / kWave];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
-    T v[kScanItems];
+    const int64_t base = item_base(blockIdx.x);
     T thread_sum = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? static_cast<T>(in[base + i]) : T(0);
-        thread_sum += v[i];
-    }
+    for (int i = 0; i < kScanItems; ++i) thread_sum += (base + i < n) ? static_cast<T>(in[base + i]) : T(0);
     T total;
-    T run = block_exclusive_sum<T>(thread_sum, s_wave, &total);
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += v[i];
-    }
+    block_exclusive_sum<T>(thread_sum, s_wave, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
@@ -69,13 +68,23 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(T *sums, int64_t nb) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_add(T *__restrict__ out, int64_t n, const T *__restrict__ sums,
-                                                         int64_t nb, int write_total) {
-    const T off = sums[blockIdx.x];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
-    for (int i = threadIdx.x; i < kScanTile; i += kScanBlock) {
-        const int64_t j = base + i;
-        if (j < n) out[j] += off;
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *in, int64_t n, T *out,
+                                                          const T *__restrict__ sums, int64_t nb, int write_total) {
+    __shared__ T s_wave[kScanBlock / kWave];
+    const int64_t base = item_base(blockIdx.x);
+    T v[kScanItems];
+    T thread_sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? static_cast<T>(in[base + i]) : T(0);
+        thread_sum += v[i];
+    }
+    T total;
+    T run = sums[blockIdx.x] + block_exclusive_sum<T>(thread_sum, s_wave, &total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
     }
     if (write_total && blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
 }
@@ -90,13 +99,14 @@ static int scan_impl(const uint32_t *in, int64_t n, T *out, bool write_total, vo
     const int64_t nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 0;
     T *sums = static_cast<T *>(ws);
     if (nb > 0) {
-        k_scan_tiles<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, out, sums);
-        SFC_LAUNCH_CHECK("k_scan_tiles");
+        k_scan_reduce<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, sums);
+        SFC_LAUNCH_CHECK("k_scan_reduce");
     }
     k_scan_sums<T><<<1, kScanBlock, 0, s>>>(sums, nb);
     SFC_LAUNCH_CHECK("k_scan_sums");
-    k_scan_add<T><<<static_cast<unsigned>(nb > 0 ? nb : 1), kScanBlock, 0, s>>>(out, n, sums, nb, write_total ? 1 : 0);
-    SFC_LAUNCH_CHECK("k_scan_add");
+    k_scan_down<T><<<static_cast<unsigned>(nb > 0 ? nb : 1), kScanBlock, 0, s>>>(in, n, out, sums, nb,
+                                                                                   write_total ? 1 : 0);
+    SFC_LAUNCH_CHECK("k_scan_down");
     return SFC_OK;
 }
 
