@@ -1187,24 +1187,34 @@ __device__ __forceinline__ void rows_block(int nch, uint64_t rows, const uint32_
 
 // Staged long rows, for a group whose records fit one block and whose rows
 // are consecutive in lane order (then its output is one region [r0, r1),
-// written strictly in order): pieces go to an LDS buffer of kRowBuf entries
-// that starts at `base` (a multiple of 4 entries); every 256 entries are
-// written out as one 16-byte store per lane, so the wave issues a quarter of
-// the stores at whole cache lines.  `front` is the end of what the pieces
-// wrote so far.
-constexpr int kRowBuf = 320;  // 256 written out at a time + up to 63 carried over
+// written strictly in order): pieces go to an LDS ring of kRowRing entries
+// (entry g of the output at g mod kRowRing) and every 256 entries are written
+// out as one 16-byte store per lane, so the wave issues a quarter of the
+// stores at whole cache lines.  Before a query's pieces fewer than 256
+// entries wait in the ring and a query adds at most one entry per record.
+// A query whose entries fit the rest of the ring (in a group of at most
+// kRowRing - 256 records, every query) writes all its pieces and then writes
+// out the full blocks; a longer one writes out the full blocks after each
+// piece of at most 64 entries, so the ring never overwrites what it still
+// holds.
+#ifndef SFC_ROW_RING
+#define SFC_ROW_RING 1024
+#endif
+constexpr uint32_t kRowRing = SFC_ROW_RING;
+static_assert((kRowRing & (kRowRing - 1)) == 0 && kRowRing >= 512, "row ring size");
 struct RowStage {
-    uint32_t *buf;  // LDS, kRowBuf entries, 16-byte aligned
+    uint32_t *buf;  // LDS, kRowRing entries, 16-byte aligned
     uint32_t *out;  // the output indices, 16-byte aligned
-    uint64_t r0, r1, base, front;
+    uint64_t r0, r1, base;  // base: the next entry to write out (a multiple of 4)
 };
 
-// Writes out entries [st.base, st.base + 256) that lie in [r0, r1) and moves
-// those past them (fewer than 64, up to st.front) to the buffer's start.
+// Writes out entries [st.base, st.base + 256) that lie in [r0, r1).
 __device__ __forceinline__ void stage_flush(RowStage &st) {
     const int lane = lane_id();
     const uint64_t g0 = st.base + 4u * static_cast<uint32_t>(lane);
-    const uint4 v = *reinterpret_cast<const uint4 *>(st.buf + 4 * lane);
+    wave_sync();
+    const uint4 v = *reinterpret_cast<const uint4 *>(st.buf + (static_cast<uint32_t>(g0) & (kRowRing - 1)));
+    wave_sync();
     if (g0 >= st.r0 && g0 + 4 <= st.r1) {
         *reinterpret_cast<uint4 *>(st.out + g0) = v;
     } else {
@@ -1213,20 +1223,16 @@ __device__ __forceinline__ void stage_flush(RowStage &st) {
         for (int i = 0; i < 4; ++i)
             if (g0 + i >= st.r0 && g0 + i < st.r1) st.out[g0 + i] = e[i];
     }
-    const uint64_t end = st.base + 256;
-    const uint32_t mv = st.front > end ? static_cast<uint32_t>(min<uint64_t>(st.front - end, kWave)) : 0u;
-    uint32_t t = 0;
-    if (static_cast<uint32_t>(lane) < mv) t = st.buf[256 + lane];
-    wave_sync();
-    if (static_cast<uint32_t>(lane) < mv) st.buf[lane] = t;
-    wave_sync();
-    st.base = end;
+    st.base += 256;
 }
 
 template <int NCH>
 __device__ __forceinline__ void rows_queries_staged(uint64_t qm, const uint32_t (&word)[kRowBlk],
                                                     const uint32_t (&pi)[kRowBlk], uint64_t start, uint32_t len,
                                                     RowStage &st) {
+    // NCH chunks hold at most 64 NCH records: with at most kRowRing - 256,
+    // every query's entries fit the ring
+    constexpr bool FIT = NCH * kWave + 256 <= static_cast<int>(kRowRing);
     for (; qm; qm &= qm - 1) {
         const int j = __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(qm)) - 1);
         const uint32_t rl = readlane_u32(len, j);
@@ -1241,20 +1247,33 @@ __device__ __forceinline__ void rows_queries_staged(uint64_t qm, const uint32_t 
             m[u] = ballot((word[u] & bit) != 0u);
             tot += static_cast<uint32_t>(__popcll(m[u]));
         }
-        const bool whole = tot <= rl;  // always, when the offsets come from this count
-        uint32_t at = 0;
+        // the row's whole (always, when the offsets come from this count) and it fits the ring
+        if (tot <= rl && (FIT || static_cast<uint32_t>(s0 - st.base) + tot <= kRowRing)) {
+            uint32_t at = static_cast<uint32_t>(s0);  // ring positions wrap, so the low word suffices
 #pragma unroll
-        for (int u = 0; u < NCH; ++u) {
-            // the piece's buffer position: below 256 while at <= rl (a flush
-            // follows every piece that reaches 256), so rel + rank < kRowBuf
-            const uint32_t rel = static_cast<uint32_t>(s0 - st.base) + at;
-            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), rel));
-            if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && (whole || at + (pos - rel) < rl)) st.buf[pos] = pi[u];
-            at += static_cast<uint32_t>(__popcll(m[u]));
-            st.front = s0 + min(at, rl);
-            if (st.front >= st.base + 256) stage_flush(st);
+            for (int u = 0; u < NCH; ++u) {
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), at));
+                if (__builtin_amdgcn_inverse_ballot_w64(m[u])) st.buf[pos & (kRowRing - 1)] = pi[u];
+                at += static_cast<uint32_t>(__popcll(m[u]));
+            }
+        } else {  // piece by piece; a shorter row takes the first of its entries
+            uint32_t at = 0;
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), at));
+                if (__builtin_amdgcn_inverse_ballot_w64(m[u]) && pos < rl)
+                    st.buf[(static_cast<uint32_t>(s0) + pos) & (kRowRing - 1)] = pi[u];
+                at += static_cast<uint32_t>(__popcll(m[u]));
+                if constexpr (!FIT) {
+                    const uint64_t front = s0 + min(at, rl);
+                    while (front >= st.base + 256) stage_flush(st);
+                }
+            }
         }
+        const uint64_t front = s0 + min(tot, rl);
+        while (front >= st.base + 256) stage_flush(st);
     }
 }
 
@@ -1309,13 +1328,9 @@ __device__ __forceinline__ void radius_fill_rows_body(const SearchArgs &a, const
         st.r0 = readlane_u64(start, 0);
         st.r1 = readlane_u64(start + len, last);
         st.base = st.r0 & ~3ull;
-        st.front = st.r0;
         const int nch = static_cast<int>(min((n + kWave - 1) / kWave, static_cast<uint32_t>(kRowBlk)));
         rows_block_staged(nch, rows, lo, hi, pi, start, len, st);
-        while (st.base < st.r1) {
-            st.front = st.r1;
-            stage_flush(st);
-        }
+        while (st.base < st.r1) stage_flush(st);
         return;
     }
     // otherwise each piece is stored straight to its row
@@ -1728,7 +1743,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_rows(SearchArgs a) {
     if (a.offsets[a.nq_total] > a.capacity) return;
     const SearchCloud C = group_cloud(a, g);
     if (!(C.r > 0.0f)) return;
-    __shared__ __align__(16) uint32_t stage_buf[kRowBuf];
+    __shared__ __align__(16) uint32_t stage_buf[kRowRing];
     radius_fill_rows_body(a, C, g - C.g0, min(v & ~kRecLongRows, static_cast<uint32_t>(kRecCap)), stage_buf);
 }
 

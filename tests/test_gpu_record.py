@@ -210,6 +210,26 @@ def test_record_long_rows_two_blocks(sfc):
     _rec_case(sfc, pts, "hilbert", 32, "sphere", 0.15)
 
 
+def test_record_long_rows_past_the_ring(sfc):
+    """Long-row groups of 769-1024 records whose rows hold more than 768
+    entries: the staged long-row fill's LDS ring (1024 entries, fewer than 256
+    waiting before a query) cannot take such a row in one go behind every
+    waiting count, so those queries write out full blocks piece by piece.
+    Tight clusters of 900 points, every cluster point a neighbour of all the
+    others; groups that span two clusters (over 1024 records) take the
+    unstaged form."""
+    rng = np.random.default_rng(41)
+    centres = np.stack(np.meshgrid(np.arange(4), np.arange(3), np.arange(2), indexing="ij"), -1).reshape(-1, 3) * 3.0
+    pts = np.concatenate([c + rng.uniform(-0.05, 0.05, (900, 3)) for c in centres]).astype(np.float32)
+    t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 64)
+    perm = t.perm().cpu().numpy().view(np.uint32)
+    c, o, idx = oracle.radius_search(pts, pts[perm], "sphere", 0.5)
+    recs = np.array([np.unique(idx[o[g]:o[min(g + 64, c.size)]]).size for g in range(0, c.size, 64)])
+    assert ((recs > 768) & (recs <= 1024)).sum() >= 10 and c.min() == 900
+    announce("record long rows past the row ring")
+    _rec_case(sfc, pts, "hilbert", 64, "sphere", 0.5)
+
+
 def test_record_fill_shorter_rows(sfc):
     """A fill given offsets with shorter rows than its count recorded (counts
     changed by the caller between the calls) writes each row's first entries,
