@@ -82,7 +82,7 @@ namespace {
 #define SFC_CHUNK 16
 #endif
 #ifndef SFC_REC_ROWBLK
-#define SFC_REC_ROWBLK 16
+#define SFC_REC_ROWBLK 20
 #endif
 constexpr int kStack = SFC_STACK;     // traversal stack entries
 constexpr int kCand = SFC_CAND;       // candidate nodes held before a sweep
@@ -1037,7 +1037,6 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
                                                      int64_t lg, uint32_t n) {
     const int lane = lane_id();
     const int64_t lr = lg * kWave + lane;
-    const int64_t gg = lg + C.g0;
     int64_t row;
     const Query q = lane_query(a, C, lr, &row);
     const int64_t orow = q.valid ? row : 0;
@@ -1123,18 +1122,18 @@ __device__ __forceinline__ void radius_fill_rec_body(RecLds &L, const SearchArgs
 }
 
 // Long rows, written one query after another: the wave holds up to kRowBlk
-// chunks of 64 records in registers (lane = record; 16 chunks cover the
+// chunks of 64 records in registers (lane = record; 20 chunks cover the
 // records of nearly every long-row group, so the wave loads nothing after its
 // first store: on this GPU a wait for a load also waits for every store
 // issued before it).  For each query the lanes whose record mask holds its
 // bit put their original index at the row's next positions (each lane's
 // rank among them from mbcnt, which also adds the entries already written).
 // A group of a cloud's own points has its rows consecutive in the output, so
-// the pieces fill one region in order: they go to an LDS buffer written out
+// the pieces fill one region in order: they go to an LDS ring written out
 // 256 entries at a time with 16-byte stores; other groups store each piece
 // straight to its row.
 constexpr int kRowBlk = SFC_REC_ROWBLK;
-static_assert(kRowBlk >= 1 && kRowBlk <= 16, "record chunks held per pass");
+static_assert(kRowBlk >= 1 && kRowBlk <= 32, "record chunks held per pass");
 
 // The queries of `qm` against NCH chunks of records: word[u] / pi[u] hold
 // chunk u's mask words (the low ones for queries 0-31, the high ones for

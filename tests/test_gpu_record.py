@@ -195,19 +195,21 @@ def test_record_fill_checks_provenance(sfc):
 
 
 def test_record_long_rows_two_blocks(sfc):
-    """Long-row groups whose records exceed the 1024 the long-row fill holds
-    at once (a second block of records is loaded after the first block's
-    stores): a uniform cube where each group of 64 queries reaches 1000-2500
-    distinct points (records), all rows long."""
+    """Long-row groups past the 1024 records of 16 chunks and past the 1280
+    of 20 chunks the long-row fill holds at once (beyond those a second block
+    of records is loaded after the first block's stores): a uniform cube
+    where each group of 64 queries reaches 220-1300 distinct points (records)
+    at r = 0.15 and 300-1900 at r = 0.18, all rows long."""
     pts = datagen.uniform(20000, seed=17)
     t = sfc.build_linear_octree(_dev(pts), "hilbert", 21, 32)
     perm = t.perm().cpu().numpy().view(np.uint32)
-    c, o, idx = oracle.radius_search(pts, pts[perm], "sphere", 0.15)
-    # records of a group = the distinct points its queries find
-    recs = [np.unique(idx[o[g]:o[min(g + 64, c.size)]]).size for g in range(0, c.size, 64)]
-    assert max(recs) > 1024 and max(recs) <= 4096 and c.mean() >= 64
-    announce("record long rows, two record blocks")
-    _rec_case(sfc, pts, "hilbert", 32, "sphere", 0.15)
+    for r, least in ((0.15, 1024), (0.18, 1280)):
+        c, o, idx = oracle.radius_search(pts, pts[perm], "sphere", r)
+        # records of a group = the distinct points its queries find
+        recs = np.array([np.unique(idx[o[g]:o[min(g + 64, c.size)]]).size for g in range(0, c.size, 64)])
+        assert (recs > least).sum() >= 3 and recs.max() <= 4096 and c.mean() >= 64
+        announce(f"record long rows, two record blocks, r={r}")
+        _rec_case(sfc, pts, "hilbert", 32, "sphere", r)
 
 
 def test_record_long_rows_past_the_ring(sfc):
@@ -216,8 +218,8 @@ def test_record_long_rows_past_the_ring(sfc):
     waiting before a query) cannot take such a row in one go behind every
     waiting count, so those queries write out full blocks piece by piece.
     Tight clusters of 900 points, every cluster point a neighbour of all the
-    others; groups that span two clusters (over 1024 records) take the
-    unstaged form."""
+    others; groups that span two clusters (1800 records) take the unstaged
+    form."""
     rng = np.random.default_rng(41)
     centres = np.stack(np.meshgrid(np.arange(4), np.arange(3), np.arange(2), indexing="ij"), -1).reshape(-1, 3) * 3.0
     pts = np.concatenate([c + rng.uniform(-0.05, 0.05, (900, 3)) for c in centres]).astype(np.float32)
