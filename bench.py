@@ -251,7 +251,8 @@ def bench_batched(args):
                      "achieved": search_bytes / search_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": search_bytes / search_ms / 1e6 / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_query": "16 + 4 + 8 + 4 mu"},
-        "autotune": {"table_ms": tune["table"], "mu_edges": tune["edges"], "cached": tune["cached"],
+        "autotune": {"table_ms": tune["table"], "whole_batch_ms": tune.get("whole", {}), "mu_edges": tune["edges"],
+                     "cached": tune["cached"],
                      "choice_histogram": {f"leaf={lf}/stage={st}/fill={'record' if rc else 'search'}": cnt
                                           for (lf, st, rc), cnt in
                                           sorted(_count(zip(leaves, stages, record)).items())}},

@@ -17,7 +17,14 @@ guessing:
      fastest leaf, with every candidate (stage, fill) pair (median of
      `repeats` timed steps after a warm-up each); recorded fills are tried
      only while the group's records fit `record_budget` bytes;
-  4. every cloud gets its group's fastest (leaf, stage, fill).
+  4. every cloud gets its group's fastest (leaf, stage, fill);
+  5. when the groups' fills differ, the whole batch is timed with those
+     fills, with every cloud on the search fill and (within the budget) with
+     every cloud recorded, each at the chosen leaves and tiles, and the
+     fastest is kept: in one batch the fills run one launch after another
+     (recorded-row kernels, then the search fill), and the recording count
+     costs every recorded cloud more than the plain count, so the groups'
+     choices need not add up to the fastest batch.
 
 Results are cached in a JSON file keyed by the batch description (sizes,
 kernels, radii, curve, candidates, budget, device name), so a repeated
@@ -47,7 +54,8 @@ def default_cache_path() -> str:
 
 def _key(sizes, kernels, radii, curve, candidates, stages, fills, buckets, budget, device) -> str:
     h = hashlib.sha256()
-    h.update(json.dumps([list(map(int, sizes)), list(map(str, kernels)), [float(x) for x in radii], str(curve),
+    h.update(json.dumps(["whole-batch fill check", list(map(int, sizes)), list(map(str, kernels)),
+                         [float(x) for x in radii], str(curve),
                          list(map(int, candidates)), list(map(int, stages)), list(map(str, fills)), int(buckets),
                          int(budget), str(device)]).encode())
     return h.hexdigest()[:32]
@@ -77,7 +85,9 @@ def tune(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, stages=S
          cache_path: str | None = None, log=None) -> dict:
     """Returns {"leaf", "stage", "record": per-cloud choices, "bucket": per-cloud
     group, "mu": per-cloud mean neighbour count, "table": {group: {"leaf=L":
-    ms, "leaf=L/stage=S/fill=F": ms}}, "edges", "cached": bool}."""
+    ms, "leaf=L/stage=S/fill=F": ms}}, "whole": {"per_group" | "search" |
+    "record": ms of the whole batch} (empty when the groups agree on the
+    fill), "edges", "cached": bool}."""
     import torch
     sizes = [int(x) for x in sizes]
     nb = len(sizes)
@@ -148,10 +158,26 @@ def tune(xyz, sizes, kernel, r, curve="hilbert", candidates=CANDIDATES, stages=S
         best[g] = (leaf, stage, fill)
     fallback = (min(candidates), 128, "search")
     choice = [best.get(int(group[c]), fallback) for c in range(nb)]
-    out = {"leaf": [int(x[0]) for x in choice], "stage": [int(x[1]) for x in choice],
-           "record": [x[2] == "record" for x in choice], "bucket": [int(x) for x in group],
+    leaves = [int(x[0]) for x in choice]
+    stages_c = [int(x[1]) for x in choice]
+    record = [x[2] == "record" for x in choice]
+    # 5. the whole batch with the groups' fills against one fill for all
+    whole = {}
+    if len(set(record)) > 1:
+        fills_whole = {"per_group": record, "search": [False] * nb}
+        if record_bytes(sizes) <= record_budget:
+            fills_whole["record"] = [True] * nb
+        for name, rec in fills_whole.items():
+            plan = BatchPlan(xyz, sizes, curve, 21, leaves, kernels, radii, record=rec, stage=stages_c)
+            whole[name] = _time_step(plan, repeats)
+            del plan
+            torch.cuda.empty_cache()
+            if log:
+                log(f"[autotune] whole batch, {name} fills: {whole[name]:.2f} ms")
+        record = fills_whole[min(whole, key=whole.get)]
+    out = {"leaf": leaves, "stage": stages_c, "record": record, "bucket": [int(x) for x in group],
            "mu": [float(x) for x in mu], "table": {str(g): t for g, t in table.items()},
-           "edges": [float(x) for x in edges]}
+           "whole": whole, "edges": [float(x) for x in edges]}
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         cache[key] = out

@@ -116,6 +116,13 @@ def test_autotune_leaf_tile_fill(tmp_path):
         assert sum(k.startswith("leaf=") and "/" not in k for k in ms) == 2
         # the default tile at the chosen leaf, then stage x fill (64 and 256, search and record)
         assert sum("/" in k for k in ms) == 5
+    # groups that chose different fills: the whole batch was timed with them and with one fill for all
+    groups = {}
+    for b, rec in zip(t["bucket"], t["record"]):
+        groups.setdefault(b, set()).add(rec)
+    assert all(len(v) == 1 for v in groups.values())
+    if t["whole"]:
+        assert {"per_group", "search", "record"} <= set(t["whole"]) and all(v > 0 for v in t["whole"].values())
     t2 = autotune.tune(xyz, SIZES, KERN, RADII, "hilbert", **kw)
     assert t2["cached"] and (t2["leaf"], t2["stage"], t2["record"]) == (t["leaf"], t["stage"], t["record"])
     # a zero record budget keeps every group on the search fill
