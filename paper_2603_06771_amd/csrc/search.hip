@@ -1661,10 +1661,17 @@ __device__ __forceinline__ bool records_valid(const SearchArgs &a) {
 
 }  // namespace
 
-// The count and search-fill kernels take their LDS from the launch's dynamic
-// allocation, sized by the host for the largest staging tile among the
-// launch's clouds; each group views it with its own cloud's layout.
+// The count and search-fill kernels come in one kernel per staging tile (a
+// kernel holding every tile's body would need the registers of the largest
+// one in every cloud); the host launches those of the tiles its clouds use,
+// each serving the groups of its own tile's clouds, with the tile's layout
+// in the launch's dynamic LDS.
 extern __shared__ __align__(16) unsigned char g_radius_lds[];
+
+// a cloud's staging tile (64, 128 or 256 points; anything else is 128)
+__device__ __forceinline__ int tile_of(const SearchCloud &C) {
+    return C.stage == 64 ? 64 : C.stage == 256 ? 256 : 128;
+}
 
 template <bool REC, int STAGE>
 __device__ __forceinline__ void radius_count_tile(const SearchArgs &a, const SearchCloud &C, int64_t lg) {
@@ -1677,28 +1684,22 @@ __device__ __forceinline__ void radius_count_tile(const SearchArgs &a, const Sea
     }
 }
 
-template <bool REC>
-__device__ __forceinline__ void radius_count_group(const SearchArgs &a, const SearchCloud &C, int64_t lg) {
-    switch (C.stage) {
-    case 64: radius_count_tile<REC, 64>(a, C, lg); break;
-    case 256: radius_count_tile<REC, 256>(a, C, lg); break;
-    default: radius_count_tile<REC, 128>(a, C, lg); break;
-    }
-}
-
-// One wave per group of 64 queries of one cloud; the cloud's kernel and
-// staging tile select the (wave-uniform) body.
-__global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) {
+// One wave per group of 64 queries of one cloud of the kernel's tile; the
+// cloud's kernel selects the (wave-uniform) body.
+template <int STAGE>
+__device__ __forceinline__ void radius_count_kernel(const SearchArgs &a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     const SearchCloud C = group_cloud(a, g);
-    radius_count_group<false>(a, C, g - C.g0);
+    if (tile_of(C) != STAGE) return;
+    radius_count_tile<false, STAGE>(a, C, g - C.g0);
 }
 
 // the count that also records the hits of every group of the recording
 // clouds (SFC_RECORD_HITS, or the cloud's own choice in a batch); groups of
 // the other clouds are counted plainly and left to k_radius_fill
-__global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
+template <int STAGE>
+__device__ __forceinline__ void radius_count_rec_kernel(const SearchArgs &a) {
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (g == 0 && lane_id() == 0) {  // the records' provenance (read by the fills, which run after this kernel)
@@ -1706,13 +1707,22 @@ __global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) {
         a.rec_tag[1] = a.tag1;
     }
     const SearchCloud C = group_cloud(a, g);
+    if (tile_of(C) != STAGE) return;
     if (C.rec) {
-        radius_count_group<true>(a, C, g - C.g0);
+        radius_count_tile<true, STAGE>(a, C, g - C.g0);
     } else {
         if (lane_id() == 0) a.rec_n[g] = kRecOverflow;
-        radius_count_group<false>(a, C, g - C.g0);
+        radius_count_tile<false, STAGE>(a, C, g - C.g0);
     }
 }
+
+// the default tile's kernels, then those of the 64- and 256-point tiles
+__global__ __launch_bounds__(64) void k_radius_count(SearchArgs a) { radius_count_kernel<128>(a); }
+__global__ __launch_bounds__(64) void k_radius_count_t64(SearchArgs a) { radius_count_kernel<64>(a); }
+__global__ __launch_bounds__(64) void k_radius_count_t256(SearchArgs a) { radius_count_kernel<256>(a); }
+__global__ __launch_bounds__(64) void k_radius_count_rec(SearchArgs a) { radius_count_rec_kernel<128>(a); }
+__global__ __launch_bounds__(64) void k_radius_count_rec_t64(SearchArgs a) { radius_count_rec_kernel<64>(a); }
+__global__ __launch_bounds__(64) void k_radius_count_rec_t256(SearchArgs a) { radius_count_rec_kernel<256>(a); }
 
 // Rows of the recorded groups that took the short-row form; the long-row
 // groups are k_radius_fill_rows' and those whose records did not fit
@@ -1757,14 +1767,12 @@ __device__ __forceinline__ void radius_fill_tile(const SearchArgs &a, const Sear
     }
 }
 
+// group g, if its cloud has the kernel's tile
+template <int STAGE>
 __device__ __forceinline__ void radius_fill_group(const SearchArgs &a, int64_t g) {
     const SearchCloud C = group_cloud(a, g);
-    const int64_t lg = g - C.g0;
-    switch (C.stage) {
-    case 64: radius_fill_tile<64>(a, C, lg); break;
-    case 256: radius_fill_tile<256>(a, C, lg); break;
-    default: radius_fill_tile<128>(a, C, lg); break;
-    }
+    if (tile_of(C) != STAGE) return;
+    radius_fill_tile<STAGE>(a, C, g - C.g0);
 }
 
 // One wave per group; or, when every cloud of the launch records its hits
@@ -1774,7 +1782,8 @@ __device__ __forceinline__ void radius_fill_group(const SearchArgs &a, int64_t g
 // per wave.
 constexpr int kFillScan = 8;
 
-__global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
+template <int STAGE>
+__device__ __forceinline__ void radius_fill_kernel(const SearchArgs &a) {
     if (a.fill_scan) {
         const int64_t g0 = xcd_item(blockIdx.x, gridDim.x) * kFillScan;
         if (g0 >= a.groups) return;
@@ -1784,15 +1793,19 @@ __global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) {
         const bool need = lane_id() < kFillScan && g < a.groups &&
                           (!valid || coherent_load(a.rec_n + g) == kRecOverflow);
         for (uint64_t m = ballot(need); m; m &= m - 1)
-            radius_fill_group(a, g0 + __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(m)) - 1));
+            radius_fill_group<STAGE>(a, g0 + __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(m)) - 1));
         return;
     }
     const int64_t g = xcd_item(blockIdx.x, gridDim.x);
     if (g >= a.groups) return;
     if (a.offsets[a.nq_total] > a.capacity) return;  // caller's buffer too small: write nothing
     if (a.rec_n && records_valid(a) && coherent_load(a.rec_n + g) != kRecOverflow) return;  // written from its records
-    radius_fill_group(a, g);
+    radius_fill_group<STAGE>(a, g);
 }
+
+__global__ __launch_bounds__(64) void k_radius_fill(SearchArgs a) { radius_fill_kernel<128>(a); }
+__global__ __launch_bounds__(64) void k_radius_fill_t64(SearchArgs a) { radius_fill_kernel<64>(a); }
+__global__ __launch_bounds__(64) void k_radius_fill_t256(SearchArgs a) { radius_fill_kernel<256>(a); }
 
 // Deferred (spread) groups: one wave per query, grid-stride over the list.
 __global__ __launch_bounds__(64) void k_radius_count_spread(SearchArgs a) {
@@ -2464,12 +2477,23 @@ int64_t record_groups(const std::vector<SearchCloud> &tab) {
 
 // dynamic LDS of the count and search-fill kernels: the layout of the
 // largest staging tile among the launch's clouds
-size_t radius_lds_bytes(const std::vector<SearchCloud> &tab, bool fill) {
-    int st = 64;
-    for (const SearchCloud &c : tab) st = std::max(st, static_cast<int>(c.stage));
-    if (st > 128) return fill ? sizeof(FillLdsT<256>) : sizeof(RadLdsT<256>);
-    if (st > 64) return fill ? sizeof(FillLdsT<128>) : sizeof(RadLdsT<128>);
-    return fill ? sizeof(FillLdsT<64>) : sizeof(RadLdsT<64>);
+// dynamic LDS of the count and search-fill kernels of one staging tile
+size_t radius_lds_bytes(int tile, bool fill) {
+    if (tile == 256) return fill ? sizeof(FillLdsT<256>) : sizeof(RadLdsT<256>);
+    if (tile == 64) return fill ? sizeof(FillLdsT<64>) : sizeof(RadLdsT<64>);
+    return fill ? sizeof(FillLdsT<128>) : sizeof(RadLdsT<128>);
+}
+
+// the staging tiles the clouds use (the host's reading of each cloud's tile
+// is the device's tile_of)
+std::vector<int> radius_tiles(const std::vector<SearchCloud> &tab) {
+    bool has[3] = {false, false, false};
+    for (const SearchCloud &c : tab) has[c.stage == 64 ? 0 : c.stage == 256 ? 2 : 1] = true;
+    std::vector<int> out;
+    if (has[1]) out.push_back(128);
+    if (has[0]) out.push_back(64);
+    if (has[2]) out.push_back(256);
+    return out;
 }
 
 // Sorts the external queries of every cloud by their code (stable, so equal
@@ -2570,13 +2594,25 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
                 k_reset_spread<<<1, 64, 0, s>>>(a.nspread);
                 SFC_LAUNCH_CHECK("k_reset_spread");
             }
-            const size_t lds = radius_lds_bytes(tab, false);
-            if (record) {
-                k_radius_count_rec<<<grid, 64, lds, s>>>(a);
-                SFC_LAUNCH_CHECK("k_radius_count_rec");
-            } else {
-                k_radius_count<<<grid, 64, lds, s>>>(a);
-                SFC_LAUNCH_CHECK("k_radius_count");
+            for (const int tile : radius_tiles(tab)) {
+                const size_t lds = radius_lds_bytes(tile, false);
+                if (record) {
+                    if (tile == 64)
+                        k_radius_count_rec_t64<<<grid, 64, lds, s>>>(a);
+                    else if (tile == 256)
+                        k_radius_count_rec_t256<<<grid, 64, lds, s>>>(a);
+                    else
+                        k_radius_count_rec<<<grid, 64, lds, s>>>(a);
+                    SFC_LAUNCH_CHECK("k_radius_count_rec");
+                } else {
+                    if (tile == 64)
+                        k_radius_count_t64<<<grid, 64, lds, s>>>(a);
+                    else if (tile == 256)
+                        k_radius_count_t256<<<grid, 64, lds, s>>>(a);
+                    else
+                        k_radius_count<<<grid, 64, lds, s>>>(a);
+                    SFC_LAUNCH_CHECK("k_radius_count");
+                }
             }
             if (a.queries) {  // only external queries are ever deferred
                 k_radius_count_spread<<<sgrid, 64, 0, s>>>(a);
@@ -2601,8 +2637,16 @@ int radius_launch(SearchArgs &a, const std::vector<SearchCloud> &tab, int64_t gr
         a.fill_scan = record && rec_groups == groups ? 1u : 0u;
         const unsigned fgrid =
             a.fill_scan ? static_cast<unsigned>(xcd_grid((groups + kFillScan - 1) / kFillScan)) : grid;
-        k_radius_fill<<<fgrid, 64, radius_lds_bytes(tab, true), s>>>(a);
-        SFC_LAUNCH_CHECK("k_radius_fill");
+        for (const int tile : radius_tiles(tab)) {
+            const size_t lds = radius_lds_bytes(tile, true);
+            if (tile == 64)
+                k_radius_fill_t64<<<fgrid, 64, lds, s>>>(a);
+            else if (tile == 256)
+                k_radius_fill_t256<<<fgrid, 64, lds, s>>>(a);
+            else
+                k_radius_fill<<<fgrid, 64, lds, s>>>(a);
+            SFC_LAUNCH_CHECK("k_radius_fill");
+        }
         if (a.queries) {
             k_radius_fill_spread<<<sgrid, 64, 0, s>>>(a);
             SFC_LAUNCH_CHECK("k_radius_fill_spread");
